@@ -1,0 +1,117 @@
+/*
+ * ldpc.h -- C ABI of the MI355X flooding sum-product LDPC decoder.
+ *
+ * The operation is the sum-product (belief-propagation) decoding of a binary
+ * LDPC code of Sec. II-B (Eqs. 4-8) in the flooding order of Algorithm 1 (all
+ * check nodes, then all variable nodes, per iteration), applied independently to
+ * a batch of received words: the "batch processing" decomposition of Sec. III-C,
+ * where every worker decodes whole words.  A syndrome test (H z^T = 0, Eq. 1)
+ * may end each word early.
+ *
+ * Conventions shared by every entry point
+ *  - H is m x n.  Edges are numbered in CSR order: check-major, variables
+ *    ascending inside a check.  Per-edge arrays (weights, gradients) use it.
+ *  - LLRs are log P(c=0)/P(c=1) (BPSK x = 1 - 2c gives lambda = 2y/sigma^2,
+ *    Eq. 4 with the ratio inverted); decisions are z_v = 1 iff L_v <= 0 (Eq. 8
+ *    for this sign).  With this sign the check rule of Eq. 5 holds for every
+ *    check degree.
+ *  - Check rule (Eq. 5, denominator 1 - prod): E_cv = 2 atanh(prod_{v'!=v} tanh(M_v'c/2)),
+ *    evaluated in FP32 in the equivalent phi form
+ *    |E_cv| = phi(sum_{v'!=v} phi(|M_v'c|)), phi(x) = log((e^x+1)/(e^x-1)),
+ *    with exclusive prefix/suffix sums and the sign as the parity of the others.
+ *  - Variable rule (Eq. 6): M_vc = clamp(L_v - E_cv, -20, 20) with
+ *    L_v = R_v + sum_c E_cv (Eq. 7).
+ *  - Messages start at E = 0, so the first check update sees M = clamp(R).
+ *  - Device pointers are device memory owned by the caller; host pointers are
+ *    read during the call only.  Work is enqueued on the given HIP stream and the
+ *    call returns without waiting.  Nothing throws across this boundary: every
+ *    entry point returns an ldpc_status; ldpc_last_error() gives the detail of
+ *    the calling thread's last failure.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDPC_OK = 0,
+  LDPC_ERR_INVALID_ARG = -1,   /* null pointer, negative size, short workspace, bad flag */
+  LDPC_ERR_BAD_MATRIX = -2,    /* malformed H (see ldpc_graph_create) */
+  LDPC_ERR_OUT_OF_MEMORY = -3, /* host or device allocation failed */
+  LDPC_ERR_DEVICE = -4,        /* a HIP call failed (detail in ldpc_last_error) */
+  LDPC_ERR_UNSUPPORTED = -5    /* degree above the kernel limits */
+} ldpc_status;
+
+typedef enum {
+  LDPC_CSR = 0, /* ptr has m+1 entries over checks, idx holds variable indices */
+  LDPC_CSC = 1  /* ptr has n+1 entries over variables, idx holds check indices */
+} ldpc_format;
+
+/* Largest check and variable degrees the kernels accept. */
+#define LDPC_MAX_CHECK_DEGREE 32
+#define LDPC_MAX_VAR_DEGREE 16
+
+/* flags of ldpc_decode / ldpc_decode_workspace_size */
+#define LDPC_LLR_F64 0x1u /* llr is double [batch][n]; rounded to FP32 once on ingest */
+
+typedef struct ldpc_graph_s *ldpc_graph_t;
+
+/*
+ * Tanner graph of H (Sec. II-B: an edge joins check c and variable v for every
+ * 1 in H[c][v]; Fig. 1).  ptr/idx are host arrays, copied; nnz = ptr[last].
+ * Returns LDPC_ERR_BAD_MATRIX if m or n <= 0, ptr is not non-decreasing from 0
+ * to nnz, an index is out of range, an entry is repeated, or a check has degree
+ * < 2; LDPC_ERR_UNSUPPORTED if a degree exceeds the limits above.  Variables of
+ * degree 0 are allowed (their posterior is the channel LLR).  The graph holds
+ * device copies of its index arrays on the current device until destroyed and
+ * must outlive the work enqueued with it.
+ */
+ldpc_status ldpc_graph_create(int32_t m, int32_t n, ldpc_format fmt, const int32_t *ptr, const int32_t *idx,
+                              int64_t nnz, ldpc_graph_t *out);
+ldpc_status ldpc_graph_destroy(ldpc_graph_t g);
+
+/* Sizes and degree extremes; any output pointer may be NULL. */
+ldpc_status ldpc_graph_info(ldpc_graph_t g, int32_t *m, int32_t *n, int64_t *edges, int32_t *max_check_deg,
+                            int32_t *max_var_deg);
+
+/* Host copies of the edge numbering: check_of_edge[e], var_of_edge[e] for e < edges (either may be NULL). */
+ldpc_status ldpc_graph_edges(ldpc_graph_t g, int32_t *check_of_edge, int32_t *var_of_edge);
+
+/* Device bytes ldpc_decode needs as workspace for this graph and batch. */
+ldpc_status ldpc_decode_workspace_size(ldpc_graph_t g, int32_t batch, uint32_t flags, size_t *bytes);
+
+/*
+ * Plain flooding decode of `batch` words (Sec. II-B, Eqs. 4-8; batch split of
+ * Sec. III-C).  llr: device [batch][n], FP32 (or FP64 with LDPC_LLR_F64).
+ * Outputs (device, [batch][n] / [batch]): hard_bits 0/1, posterior L_v (FP32),
+ * iters_used.  With early_stop != 0 a word stops at the first t in 0..max_iters
+ * whose decisions satisfy H z^T = 0 (t = 0 tests the channel decisions); its
+ * outputs are those of iteration t.  Otherwise every word runs max_iters.
+ * max_iters = 0 returns the channel LLRs.  batch = 0 is a no-op.
+ * workspace: device, >= ldpc_decode_workspace_size bytes, 256-byte aligned;
+ * its contents need no initialisation and are garbage afterwards.
+ */
+ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
+                        uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used, void *workspace,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* Decode with an explicit launch shape: waves per workgroup (1..16). Same contract as ldpc_decode. */
+ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
+                               uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
+                               void *workspace, size_t ws_bytes, int32_t waves, hipStream_t stream);
+
+const char *ldpc_status_string(ldpc_status s);
+const char *ldpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

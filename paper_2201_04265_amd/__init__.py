@@ -1,0 +1,15 @@
+"""MI355X flooding sum-product LDPC decoding (binding over the C ABI of include/ldpc.h).
+
+Every decoding step runs in the HIP kernels of libldpc_hip.so; this module only
+marshals arguments: it passes torch tensors' device pointers and the current
+HIP stream to the C entry points.  There is no CPU fallback: if the library is
+missing the calls raise.
+
+    g = Graph.from_csr(m, n, indptr, indices)
+    hard, post, iters = decode(g, llr, max_iters=50, early_stop=True)
+"""
+from __future__ import annotations
+
+from ._lib import LdpcError, lib, library_path  # noqa: F401
+from .graph import Graph  # noqa: F401
+from .decoder import decode, workspace_size  # noqa: F401

@@ -1,0 +1,66 @@
+"""ctypes loader of libldpc_hip.so and the argument types of every exported entry point."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  -- loads the HIP runtime the library binds to (same soname)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libldpc_hip.so")
+
+_i32, _i64, _u32, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
+_pi32, _pi64, _psz = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)
+
+# name -> (argtypes, restype); mirrors include/ldpc.h
+SIGNATURES = {
+    "ldpc_graph_create": ([_i32, _i32, ctypes.c_int, _p, _p, _i64, ctypes.POINTER(_p)], ctypes.c_int),
+    "ldpc_graph_destroy": ([_p], ctypes.c_int),
+    "ldpc_graph_info": ([_p, _pi32, _pi32, _pi64, _pi32, _pi32], ctypes.c_int),
+    "ldpc_graph_edges": ([_p, _p, _p], ctypes.c_int),
+    "ldpc_decode_workspace_size": ([_p, _i32, _u32, _psz], ctypes.c_int),
+    "ldpc_decode": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
+    "ldpc_decode_config": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _i32, _p],
+                           ctypes.c_int),
+    "ldpc_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "ldpc_last_error": ([], ctypes.c_char_p),
+}
+
+LLR_F64 = 0x1
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str):
+        super().__init__(f"{fn} failed: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"HIP decoder library missing: {library_path} (build it with __graft_entry__.build())")
+    h = ctypes.CDLL(library_path)
+    for name, (args, res) in SIGNATURES.items():
+        f = getattr(h, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = h
+    return h
+
+
+def check(fn: str, status: int) -> None:
+    if status != 0:
+        h = lib()
+        detail = h.ldpc_last_error().decode(errors="replace")
+        raise LdpcError(fn, status, f"{h.ldpc_status_string(status).decode()}: {detail}")
+
+
+def stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream

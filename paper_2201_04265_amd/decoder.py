@@ -1,0 +1,54 @@
+"""Plain flooding decode (ldpc_decode): argument marshalling for torch device tensors."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import LLR_F64, check, lib, stream_handle
+from .graph import Graph
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_size(graph: Graph, batch: int, f64: bool = False) -> int:
+    out = ctypes.c_size_t()
+    check("ldpc_decode_workspace_size",
+          lib().ldpc_decode_workspace_size(graph.handle, int(batch), LLR_F64 if f64 else 0, ctypes.byref(out)))
+    return out.value
+
+
+def decode(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = True, waves: int | None = None,
+           workspace: torch.Tensor | None = None, out=None, stream=None):
+    """Decode llr [B, n] (cuda float32 or float64).  Returns (hard u8 [B,n], posterior f32 [B,n], iters i32 [B])."""
+    if not llr.is_cuda or llr.dim() != 2 or llr.shape[1] != graph.n:
+        raise ValueError("llr must be a cuda tensor of shape [B, n]")
+    if llr.dtype not in (torch.float32, torch.float64):
+        raise ValueError("llr must be float32 or float64")
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    f64 = llr.dtype == torch.float64
+    dev = llr.device
+    if out is None:
+        hard = torch.empty((B, graph.n), dtype=torch.uint8, device=dev)
+        post = torch.empty((B, graph.n), dtype=torch.float32, device=dev)
+        iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    else:
+        hard, post, iters = out
+    need = workspace_size(graph, B, f64)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    flags = LLR_F64 if f64 else 0
+    h = lib()
+    s = ctypes.c_void_p(stream_handle(stream))
+    if waves is None:
+        st = h.ldpc_decode(graph.handle, _ptr(llr), B, int(max_iters), int(bool(early_stop)), flags, _ptr(hard),
+                           _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(), s)
+    else:
+        st = h.ldpc_decode_config(graph.handle, _ptr(llr), B, int(max_iters), int(bool(early_stop)), flags,
+                                  _ptr(hard), _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(),
+                                  int(waves), s)
+    check("ldpc_decode", st)
+    return hard, post, iters

@@ -1,0 +1,173 @@
+"""Parity of the plain HIP decoder (ldpc_decode) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from parity import assert_parity, compare
+from synth import codes, gf2, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2201_04265_amd as P
+
+    assert torch.cuda.is_available()
+    return P
+
+
+def gpu_decode(P, g, llr, T, es=True, waves=None):
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    hard, post, iters = P.decode(g, t, T, es, waves=waves)
+    torch.cuda.synchronize()
+    return hard.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+
+
+def test_c1_full_parity(P, oracle_lib):
+    """(3,6) n=96 Gallager band, 1000 words, 2.0 dB, FP64 LLRs rounded on ingest, 20 iterations."""
+    code = workloads.code("c1")
+    wd = workloads.words("c1", 1, 0, 2.0, 0, 1000, fp32=False)
+    g = P.Graph.from_code(code)
+    oh, op, oi, _ = oracle_lib.decode(code, wd.llr, 20, True)
+    gh, gp, gi = gpu_decode(P, g, wd.llr, 20)
+    st = compare(oh, op, oi, gh, gp, gi)
+    print("C1", st)
+    assert_parity(st)
+    # BER identical
+    assert np.mean(gh != wd.cw) == np.mean(oh != wd.cw) or st["tie_exceptions"] > 0
+
+
+@pytest.mark.parametrize("waves", [1, 3, 8, 16])
+def test_launch_shapes_agree_bitwise(P, waves):
+    code = workloads.code("c1")
+    wd = workloads.words("c1", 1, 0, 1.5, 0, 300, fp32=True)
+    g = P.Graph.from_code(code)
+    ref = gpu_decode(P, g, wd.llr, 20, True, waves=8)
+    out = gpu_decode(P, g, wd.llr, 20, True, waves=waves)
+    for a, b in zip(ref, out):
+        assert np.array_equal(a, b)
+
+
+def test_repeat_is_deterministic(P):
+    code = workloads.code("c1")
+    wd = workloads.words("c1", 1, 0, 1.0, 0, 640, fp32=True)
+    g = P.Graph.from_code(code)
+    a = gpu_decode(P, g, wd.llr, 20)
+    b = gpu_decode(P, g, wd.llr, 20)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_irregular_codes_ragged_batches(P, oracle_lib, seed):
+    """Irregular codes with odd and even check degrees in [2, 20]; batch not a multiple of 64."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(40, 300))
+    m = int(rng.integers(n // 4, n // 2))
+    chk, var = [], []
+    for c in range(m):
+        d = int(rng.integers(2, 21))
+        vs = rng.choice(n, size=min(d, n), replace=False)
+        chk += [c] * len(vs)
+        var += list(vs)
+    code = codes.from_edges(m, n, np.array(chk), np.array(var))
+    B = int(rng.integers(1, 200))
+    llr = rng.normal(2.0, 2.0, size=(B, n)).astype(np.float32)  # all-zero word through a noisy channel
+    g = P.Graph.from_code(code)
+    oh, op, oi, _ = oracle_lib.decode(code, llr, 15, True)
+    gh, gp, gi = gpu_decode(P, g, llr, 15)
+    st = compare(oh, op, oi, gh, gp, gi, post_cut=15)
+    print(seed, n, m, B, st)
+    assert_parity(st, allow_tie_fraction=0.02)
+
+
+def test_noiseless_and_zero_iterations(P):
+    code = workloads.code("c2")
+    wd = workloads.words("c2", 2, 0, 2.0, 0, 130, fp32=True)
+    g = P.Graph.from_code(code)
+    clean = (2.0 * (1.0 - 2.0 * wd.cw.astype(np.float32)) / wd.sigma2).astype(np.float32)
+    h, p, i = gpu_decode(P, g, clean, 50)
+    assert np.all(i == 0) and np.array_equal(h, wd.cw) and np.array_equal(p, clean)
+    h, p, i = gpu_decode(P, g, wd.llr, 0, es=False)
+    assert np.all(i == 0) and np.array_equal(p, wd.llr) and np.array_equal(h, (wd.llr <= 0).astype(np.uint8))
+
+
+def test_empty_batch_is_noop(P):
+    code = workloads.code("c1")
+    g = P.Graph.from_code(code)
+    t = torch.zeros((0, code.n), dtype=torch.float32, device="cuda")
+    hard, post, iters = P.decode(g, t, 20)
+    assert hard.shape == (0, code.n) and iters.shape == (0,)
+
+
+def test_fixed_iterations_without_early_stop(P, oracle_lib):
+    code = workloads.code("c1")
+    wd = workloads.words("c1", 1, 0, 2.0, 0, 200, fp32=True)
+    g = P.Graph.from_code(code)
+    oh, op, oi, _ = oracle_lib.decode(code, wd.llr, 12, False)
+    gh, gp, gi = gpu_decode(P, g, wd.llr, 12, es=False)
+    assert np.all(gi == 12)
+    assert_parity(compare(oh, op, oi, gh, gp, gi))
+
+
+def test_codeword_sign_flip_symmetry_bitexact(P):
+    """Negating the LLRs on a codeword's support negates the posteriors exactly (IEEE negation is exact)."""
+    code = workloads.code("c2")
+    s = workloads.systematic("c2")
+    wd = workloads.words("c2", 2, 1, 1.5, 0, 192, fp32=True)
+    c2 = s.encode(np.random.default_rng(1).integers(0, 2, size=(192, s.k), dtype=np.uint8))
+    flip = (1.0 - 2.0 * c2).astype(np.float32)
+    g = P.Graph.from_code(code)
+    h1, p1, i1 = gpu_decode(P, g, wd.llr, 50)
+    h2, p2, i2 = gpu_decode(P, g, wd.llr * flip, 50)
+    assert np.array_equal(i1, i2)
+    assert np.array_equal(p2, p1 * flip)
+    nz = p1 != 0
+    assert np.array_equal((h2 ^ c2)[nz], h1[nz])
+
+
+def test_early_stop_matches_first_zero_syndrome(P, oracle_lib):
+    code = workloads.code("c1")
+    wd = workloads.words("c1", 1, 0, 1.5, 0, 128, fp32=True)
+    g = P.Graph.from_code(code)
+    _, p_es, i_es = gpu_decode(P, g, wd.llr, 20, True)
+    for t in range(0, 21):
+        h_t, p_t, _ = gpu_decode(P, g, wd.llr, t, es=False)
+        ok = oracle_lib.syndrome_ok(code, h_t) == 1
+        first = (i_es == t)
+        if t < 20:
+            assert np.all(ok[first])  # words stopped before the limit satisfy H z^T = 0 at their t
+        assert np.array_equal(p_t[first], p_es[first])  # and report that iteration's posterior
+        assert not np.any(ok & (i_es > t))  # no earlier zero syndrome was skipped
+
+
+@pytest.mark.parametrize("ebn0", [1.0, 2.0, 3.0])
+def test_c2_full_size_sampled_parity(P, oracle_lib, ebn0):
+    """(3,6) n=4096, the full 65536-word batch at 50 iterations; 96 words checked against the oracle."""
+    code = workloads.code("c2")
+    B = workloads.C2["batch"]
+    snr_key = workloads.C2["ebn0s"].index(ebn0)
+    g = P.Graph.from_code(code)
+    wd = workloads.words("c2", 2, snr_key, ebn0, 0, B, fp32=True)
+    gh, gp, gi = gpu_decode(P, g, wd.llr, 50)
+    rng = np.random.default_rng(int(ebn0 * 10))
+    idx = np.sort(np.concatenate([rng.choice(B, 64, replace=False), np.arange(B - 32, B)]))
+    oh, op, oi, _ = oracle_lib.decode(code, wd.llr[idx], 50, True)
+    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx])
+    print("C2", ebn0, st, "mean iters", gi.mean(), "BER", np.mean(gh != wd.cw))
+    assert_parity(st, allow_tie_fraction=0.02)
+
+
+def test_c3_qc_sampled_parity(P, oracle_lib):
+    """QC 22x44 protograph lifted by Z=256 (n=11264), 16384 words at 1.5 dB, 30 iterations; 48 words checked."""
+    code = workloads.code("c3")
+    B = workloads.C3["batch"]
+    g = P.Graph.from_code(code)
+    wd = workloads.words("c3", 3, 0, 1.5, 0, B, fp32=True)
+    gh, gp, gi = gpu_decode(P, g, wd.llr, 30)
+    idx = np.sort(np.random.default_rng(3).choice(B, 48, replace=False))
+    oh, op, oi, _ = oracle_lib.decode(code, wd.llr[idx], 30, True)
+    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx])
+    print("C3", st, "mean iters", gi.mean(), "BER", np.mean(gh != wd.cw))
+    assert_parity(st, allow_tie_fraction=0.05)
