@@ -18,46 +18,75 @@ constexpr float kLmax = 20.0f;  // saturation of variable-to-check messages
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// phi(x) = log((e^x + 1) / (e^x - 1)) = log1p(2 / expm1(x)) for x >= 0, the
-// magnitude map of the tanh rule: 2 atanh(prod tanh(a_i / 2)) = phi(sum phi(a_i)).
-// phi(0) = +inf and phi(+inf) = 0, so a zero input message zeroes the others.
-// expm1 / log1p keep full relative accuracy for small x and for large x.
-__device__ __forceinline__ float phi(float x) { return log1pf(2.0f * __builtin_amdgcn_rcpf(expm1f(x))); }
+// phi(x) = log((e^x + 1) / (e^x - 1)) = 2 atanh(e^-x) for x >= 0: the magnitude map
+// of the tanh rule, 2 atanh(prod tanh(a_i / 2)) = phi(sum phi(a_i)).  phi(0) = +inf
+// and phi(+inf) = 0, so a zero input message zeroes the others.
+// Evaluated from the hardware exp2 / log2 / reciprocal with two branch-free paths
+// (relative error a few 1e-7 over [0, inf)):
+//   x >= 1.386 (q = e^-x <= 1/4): the odd series 2 atanh(q) = 2q (1 + q^2/3 + ... + q^10/11),
+//                                 truncation < 5e-9;
+//   x <  1.386: phi = log((2 - d) / d) with d = 1 - e^-x, where d comes from the Taylor
+//               series of 1 - e^-x for x < 0.3 (no cancellation) and from 1 - q above.
+// e^-x is 2^-(x log2 e) with the product split in two parts, so q keeps ~1 ulp for x <= 20.
+__device__ __forceinline__ float phi(float x) {
+  constexpr float kL2eHi = 1.44269502162933349609375f;  // log2(e) rounded to float
+  constexpr float kL2eLo = 1.925963033500011079e-08f;   // log2(e) - kL2eHi
+  constexpr float kLn2 = 0.693147180559945309f;
+  x = fminf(x, 100.0f);  // phi(100) < 1e-43: the result is 0 either way, the split stays finite
+  const float y = x * kL2eHi;
+  const float ey = fmaf(x, kL2eHi, -y) + x * kL2eLo;
+  float q = __builtin_amdgcn_exp2f(-y);
+  q = fmaf(-q, ey * kLn2, q);  // 2^-(y + ey) ~ 2^-y (1 - ey ln 2)
+  const float s = q * q;
+  float p = fmaf(s, 1.0f / 11.0f, 1.0f / 9.0f);
+  p = fmaf(s, p, 1.0f / 7.0f);
+  p = fmaf(s, p, 1.0f / 5.0f);
+  p = fmaf(s, p, 1.0f / 3.0f);
+  p = fmaf(s, p, 1.0f);
+  const float big = 2.0f * q * p;
+  float t = fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f);
+  t = fmaf(x, t, 1.0f / 120.0f);
+  t = fmaf(x, t, -1.0f / 24.0f);
+  t = fmaf(x, t, 1.0f / 6.0f);
+  t = fmaf(x, t, -0.5f);
+  t = fmaf(x, t, 1.0f);
+  const float d = x < 0.3f ? x * t : 1.0f - q;
+  const float r = (2.0f - d) * __builtin_amdgcn_rcpf(d);
+  const float small = __builtin_amdgcn_logf(r) * kLn2;
+  return x >= 1.386f ? big : small;
+}
 
 __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLmax), kLmax); }
 
 // Check-node update (Eq. 5) of one check for the 64 words of a tile.
-//   Lt: posterior L [n][64]; Et: c->v messages [nnz][64] (read old, write new).
-//   M_j = clamp(L_vj - E_old_j) (E_old taken as 0 when !use_old), then
-//   E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from
-//   a prefix and a suffix (no total-minus-self), sign_j = parity of the other signs.
-// Returns the parity of the hard decisions [L <= 0] over the check: the
-// syndrome bit of the decisions the messages were computed from.
+//   Mt: v->c messages [nnz][64] (already clamped); Et: new c->v messages [nnz][64];
+//   Zt: hard-decision masks [n] (bit l = decision of lane l's word).
+//   E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from a
+//   prefix and a suffix (no total-minus-self), sign_j = parity of the other signs.
+// Returns the parity of the decisions over the check: the syndrome bit (Eq. 1) of
+// the decisions the incoming messages were computed with.
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 template <int DC>
-__device__ __forceinline__ int check_update(const float *__restrict__ Lt, float *__restrict__ Et,
-                                            const int32_t *__restrict__ col_idx, int e0, int dc, int lane,
-                                            bool use_old, bool store) {
+__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et,
+                                            const unsigned long long *Zt, const int32_t *__restrict__ col_idx,
+                                            int e0, int dc, int lane, bool store) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
-  float lv[DMAX], eo[DMAX], ph[DMAX], pre[DMAX];
+  float mv[DMAX], ph[DMAX], pre[DMAX];
+  unsigned long long zx = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      const int v = col_idx[e0 + j];
-      lv[j] = Lt[v * TW + lane];
-      eo[j] = Et[(e0 + j) * TW + lane];
+      mv[j] = Mt[(e0 + j) * TW + lane];
+      zx ^= Zt[col_idx[e0 + j]];
     }
   }
-  int par = 0;
   uint32_t sg = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      par ^= (lv[j] <= 0.0f) ? 1 : 0;
-      const float mm = clamp_msg(use_old ? lv[j] - eo[j] : lv[j]);
-      sg |= (mm < 0.0f ? 1u : 0u) << j;
-      ph[j] = phi(fabsf(mm));
+      sg |= (mv[j] < 0.0f ? 1u : 0u) << j;
+      ph[j] = phi(fabsf(mv[j]));
     }
   }
   float acc = 0.0f;
@@ -79,25 +108,58 @@ __device__ __forceinline__ int check_update(const float *__restrict__ Lt, float 
       suf += ph[j];
     }
   }
-  return par;
+  return (int)((zx >> lane) & 1ull);
 }
 
-// Variable-node sum (Eq. 7): R_v + sum of the incoming c->v messages in
-// ascending check order.  DV as DC above.
+// Posterior of one variable (Eq. 7): R_v + the incoming c->v messages in ascending
+// check order.  Also returns the running prefixes pre[j] = R_v + sum_{i<j} E_i and
+// the messages themselves for the exclusive sums of Eq. 6.  DV as DC above.
 template <int DV>
-__device__ __forceinline__ float var_sum(const float *__restrict__ Rt, const float *__restrict__ Et,
-                                         const int32_t *__restrict__ var_edges, int p0, int dv, int v, int lane) {
+__device__ __forceinline__ float var_posterior(float r, const float *__restrict__ Et,
+                                               const int32_t *__restrict__ var_edges, int p0, int dv, int lane,
+                                               float *ev, float *pre, int *eid) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
   constexpr bool FIXED = DV > 0;
-  float ev[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j)
-    if (FIXED || j < dv) ev[j] = Et[var_edges[p0 + j] * TW + lane];
-  float s = Rt[v * TW + lane];
+  for (int j = 0; j < DMAX; ++j) {
+    if (FIXED || j < dv) {
+      eid[j] = var_edges[p0 + j];
+      ev[j] = Et[eid[j] * TW + lane];
+    }
+  }
+  float acc = r;
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j)
-    if (FIXED || j < dv) s += ev[j];
-  return s;
+  for (int j = 0; j < DMAX; ++j) {
+    if (FIXED || j < dv) {
+      pre[j] = acc;
+      acc += ev[j];
+    }
+  }
+  return acc;
+}
+
+// Variable-node update: posterior L (Eq. 7) -> decision mask Zt[v] (Eq. 8, z = [L <= 0]),
+// and the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6) as prefix + suffix.
+template <int DV>
+__device__ __forceinline__ void var_update(const float *__restrict__ Rt, const float *__restrict__ Et,
+                                           float *__restrict__ Mt, unsigned long long *Zt,
+                                           const int32_t *__restrict__ var_edges, int p0, int dv, int v, int lane,
+                                           bool store) {
+  constexpr int DMAX = DV > 0 ? DV : -DV;
+  constexpr bool FIXED = DV > 0;
+  float ev[DMAX], pre[DMAX];
+  int eid[DMAX];
+  const float L = var_posterior<DV>(Rt[v * TW + lane], Et, var_edges, p0, dv, lane, ev, pre, eid);
+  const unsigned long long z = __ballot(L <= 0.0f);
+  if (lane == 0) Zt[v] = z;
+  float suf = 0.0f;
+#pragma unroll
+  for (int j = DMAX - 1; j >= 0; --j) {
+    if (FIXED || j < dv) {
+      if (store) Mt[eid[j] * TW + lane] = clamp_msg(pre[j] + suf);
+      suf += ev[j];
+    }
+  }
 }
 
 }  // namespace ldpc

@@ -31,7 +31,7 @@ def test_c1_full_parity(P, oracle_lib):
     g = P.Graph.from_code(code)
     oh, op, oi, _ = oracle_lib.decode(code, wd.llr, 20, True)
     gh, gp, gi = gpu_decode(P, g, wd.llr, 20)
-    st = compare(oh, op, oi, gh, gp, gi)
+    st = compare(oh, op, oi, gh, gp, gi, oracle_lib, code, wd.llr, 20)
     print("C1", st)
     assert_parity(st)
     # BER identical
@@ -77,7 +77,7 @@ def test_random_irregular_codes_ragged_batches(P, oracle_lib, seed):
     g = P.Graph.from_code(code)
     oh, op, oi, _ = oracle_lib.decode(code, llr, 15, True)
     gh, gp, gi = gpu_decode(P, g, llr, 15)
-    st = compare(oh, op, oi, gh, gp, gi, post_cut=15)
+    st = compare(oh, op, oi, gh, gp, gi, oracle_lib, code, llr, 15)
     print(seed, n, m, B, st)
     assert_parity(st, allow_tie_fraction=0.02)
 
@@ -108,7 +108,7 @@ def test_fixed_iterations_without_early_stop(P, oracle_lib):
     oh, op, oi, _ = oracle_lib.decode(code, wd.llr, 12, False)
     gh, gp, gi = gpu_decode(P, g, wd.llr, 12, es=False)
     assert np.all(gi == 12)
-    assert_parity(compare(oh, op, oi, gh, gp, gi))
+    assert_parity(compare(oh, op, oi, gh, gp, gi, oracle_lib, code, wd.llr, 12, False))
 
 
 def test_codeword_sign_flip_symmetry_bitexact(P):
@@ -154,7 +154,7 @@ def test_c2_full_size_sampled_parity(P, oracle_lib, ebn0):
     rng = np.random.default_rng(int(ebn0 * 10))
     idx = np.sort(np.concatenate([rng.choice(B, 64, replace=False), np.arange(B - 32, B)]))
     oh, op, oi, _ = oracle_lib.decode(code, wd.llr[idx], 50, True)
-    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx])
+    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx], oracle_lib, code, wd.llr[idx], 50)
     print("C2", ebn0, st, "mean iters", gi.mean(), "BER", np.mean(gh != wd.cw))
     assert_parity(st, allow_tie_fraction=0.02)
 
@@ -168,6 +168,6 @@ def test_c3_qc_sampled_parity(P, oracle_lib):
     gh, gp, gi = gpu_decode(P, g, wd.llr, 30)
     idx = np.sort(np.random.default_rng(3).choice(B, 48, replace=False))
     oh, op, oi, _ = oracle_lib.decode(code, wd.llr[idx], 30, True)
-    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx])
+    st = compare(oh, op, oi, gh[idx], gp[idx], gi[idx], oracle_lib, code, wd.llr[idx], 30)
     print("C3", st, "mean iters", gi.mean(), "BER", np.mean(gh != wd.cw))
     assert_parity(st, allow_tie_fraction=0.05)
