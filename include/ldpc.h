@@ -19,8 +19,9 @@
  *    evaluated in FP32 in the equivalent phi form
  *    |E_cv| = phi(sum_{v'!=v} phi(|M_v'c|)), phi(x) = log((e^x+1)/(e^x-1)),
  *    with exclusive prefix/suffix sums and the sign as the parity of the others.
- *  - Variable rule (Eq. 6): M_vc = clamp(L_v - E_cv, -20, 20) with
- *    L_v = R_v + sum_c E_cv (Eq. 7).
+ *  - Variable rule (Eq. 6): M_vc = clamp(R_v + sum_{c'!=c} E_c'v, -20, 20), the
+ *    exclusive sum formed from a prefix and a suffix; posterior (Eq. 7)
+ *    L_v = R_v + sum_c E_cv, summed in ascending check order.
  *  - Messages start at E = 0, so the first check update sees M = clamp(R).
  *  - Device pointers are device memory owned by the caller; host pointers are
  *    read during the call only.  Work is enqueued on the given HIP stream and the
@@ -106,6 +107,68 @@ ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t 
 ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
                                uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
                                void *workspace, size_t ws_bytes, int32_t waves, hipStream_t stream);
+
+/* ---- batched persistent form --------------------------------------------- */
+
+/* Most codes one batched launch serves. */
+#define LDPC_MAX_CODES 8
+
+/* One code's share of a batched decode; all pointers are device memory. */
+typedef struct {
+  const float *llr;   /* [batch][n] FP32 channel LLRs */
+  int32_t batch;      /* words of this code (>= 0) */
+  int32_t max_iters;  /* iteration limit of this code (>= 0) */
+  uint8_t *hard_bits; /* [batch][n] out */
+  float *posterior;   /* [batch][n] out */
+  int32_t *iters_used;/* [batch] out */
+} ldpc_job;
+
+/* Launch shape of a batched decode: waves per workgroup (0 = 16) and 64-word
+ * slots (workgroups) per code (0 = automatic: the resident capacity of the GPU
+ * shared in proportion to words x edges, at most one slot per 64 words). */
+typedef struct {
+  int32_t waves;
+  int32_t slots[LDPC_MAX_CODES];
+} ldpc_multi_shape;
+
+/* Shape ldpc_decode_multi would use (automatic slot counts filled in) and its workspace size. */
+ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                               const ldpc_multi_shape *shape, ldpc_multi_shape *resolved, size_t *ws_bytes);
+
+/*
+ * Batched decode of the words of up to LDPC_MAX_CODES codes in one persistent
+ * launch (the batch processing of Sec. III-C with a shared work queue).  Each
+ * 64-lane slot holds words of one code; a word that stops (the syndrome test of
+ * Eq. 1 with early_stop, or its code's max_iters) writes its outputs and its lane
+ * takes the next word of that code.  Per word the arithmetic and the outputs are
+ * identical (bit for bit) to ldpc_decode with the same early_stop and max_iters.
+ * orders: NULL, or per code NULL or a device permutation of 0..batch-1 giving the
+ * order in which words are taken (outputs stay at each word's own index).
+ * workspace: device, >= ldpc_multi_resolve's size, 256-byte aligned; no
+ * initialisation needed.  Enqueued on `stream`.
+ */
+ldpc_status ldpc_decode_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                              const int32_t *const *orders, int32_t early_stop, const ldpc_multi_shape *shape,
+                              void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* A batched decode captured once into a HIP graph (fixed pointers and shapes) and replayed. */
+typedef struct ldpc_plan_s *ldpc_plan_t;
+/* Captures the launch sequence of ldpc_decode_multi on capture_stream (a non-default stream). */
+ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                                   const int32_t *const *orders, int32_t early_stop, const ldpc_multi_shape *shape,
+                                   void *workspace, size_t ws_bytes, hipStream_t capture_stream, ldpc_plan_t *out);
+ldpc_status ldpc_plan_launch(ldpc_plan_t plan, hipStream_t stream);
+ldpc_status ldpc_plan_destroy(ldpc_plan_t plan);
+
+/*
+ * Autotuner: times candidate shapes (waves per workgroup x slot scale) of this
+ * batched decode on the given inputs and returns the fastest in *best (and its
+ * time in *best_ms).  Runs the decode several times, writing the jobs' outputs;
+ * allocates and frees its own temporary workspace.  Synchronises `stream`.
+ */
+ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                                const int32_t *const *orders, int32_t early_stop, hipStream_t stream,
+                                ldpc_multi_shape *best, float *best_ms);
 
 const char *ldpc_status_string(ldpc_status s);
 const char *ldpc_last_error(void);

@@ -13,3 +13,4 @@ from __future__ import annotations
 from ._lib import LdpcError, lib, library_path  # noqa: F401
 from .graph import Graph  # noqa: F401
 from .decoder import decode, workspace_size  # noqa: F401
+from .multi import Batch, Plan, Shape, decode_multi, tuned_shape  # noqa: F401

@@ -22,6 +22,13 @@ SIGNATURES = {
     "ldpc_decode": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
     "ldpc_decode_config": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _i32, _p],
                            ctypes.c_int),
+    "ldpc_multi_resolve": ([_p, _i32, _p, _p, _p, _psz], ctypes.c_int),
+    "ldpc_decode_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
+    "ldpc_plan_create_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.c_size_t, _p, ctypes.POINTER(_p)],
+                               ctypes.c_int),
+    "ldpc_plan_launch": ([_p, _p], ctypes.c_int),
+    "ldpc_plan_destroy": ([_p], ctypes.c_int),
+    "ldpc_autotune_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ldpc_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "ldpc_last_error": ([], ctypes.c_char_p),
 }

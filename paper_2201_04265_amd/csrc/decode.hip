@@ -19,121 +19,14 @@
 // The egress recomputes each word's final posterior from its own E buffer with the
 // same summation as the variable phase, so it equals the L whose decisions stopped it.
 #include "internal.h"
-#include "spa_core.h"
+#include "tile.h"
 
 namespace ldpc {
-
-struct TileState {
-  float *E0, *E1, *M, *R;
-  unsigned long long *Z;
-};
-
-__device__ __forceinline__ TileState tile_state(float *wsE0, float *wsE1, float *wsM, float *wsR,
-                                                unsigned long long *wsZ, const GraphDev &g, int tile) {
-  TileState s;
-  const size_t eoff = (size_t)tile * (size_t)g.nnz * TW;
-  const size_t voff = (size_t)tile * (size_t)g.n * TW;
-  s.E0 = wsE0 + eoff;
-  s.E1 = wsE1 + eoff;
-  s.M = wsM + eoff;
-  s.R = wsR + voff;
-  s.Z = wsZ + (size_t)tile * (size_t)g.n;
-  return s;
-}
-
-template <int DV>
-__device__ __forceinline__ void var_range(const GraphDev &g, int v, int &p0, int &dv) {
-  if (DV > 0) {
-    p0 = v * DV;
-    dv = DV;
-  } else {
-    p0 = g.var_ptr[v];
-    dv = g.var_ptr[v + 1] - p0;
-  }
-}
-
-template <int DC>
-__device__ __forceinline__ void check_range(const GraphDev &g, int c, int &e0, int &dc) {
-  if (DC > 0) {
-    e0 = c * DC;
-    dc = DC;
-  } else {
-    e0 = g.row_ptr[c];
-    dc = g.row_ptr[c + 1] - e0;
-  }
-}
-
-// [B][n] channel LLRs -> R of the tile (through 64 x 64 LDS blocks), the first
-// v->c messages M = clamp(R) on every edge, and the channel decisions Z.
-template <int DV>
-__device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__restrict__ llr32,
-                                            const double *__restrict__ llr64, int cw0, int nvalid, TileState st,
-                                            float (*stage)[TW + 1], int wave, int W, int lane) {
-  const int n = g.n;
-  for (int v0 = 0; v0 < n; v0 += TW) {
-    for (int r = wave; r < TW; r += W) {
-      float x = 0.0f;
-      const int v = v0 + lane;
-      if (r < nvalid && v < n) {
-        const size_t off = (size_t)(cw0 + r) * (size_t)n + (size_t)v;
-        x = llr64 ? (float)llr64[off] : llr32[off];
-      }
-      stage[r][lane] = x;
-    }
-    __syncthreads();
-    for (int q = wave; q < TW && v0 + q < n; q += W) {
-      const int v = v0 + q;
-      const float x = stage[lane][q];
-      st.R[v * TW + lane] = x;
-      const unsigned long long z = __ballot(x <= 0.0f);
-      if (lane == 0) st.Z[v] = z;
-      int p0, dv;
-      var_range<DV>(g, v, p0, dv);
-      const float mx = clamp_msg(x);
-      for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
-    }
-    __syncthreads();
-  }
-}
-
-// Final posterior of each lane's word from its own E buffer -> post and hard [B][n].
-template <int DV>
-__device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int my_iters, int cw0, int nvalid,
-                                            float *__restrict__ post, uint8_t *__restrict__ hard,
-                                            float (*stage)[TW + 1], int wave, int W, int lane) {
-  constexpr int DMAX = DV > 0 ? DV : -DV;
-  const int n = g.n;
-  const float *Eb = (my_iters & 1) ? st.E1 : st.E0;
-  for (int v0 = 0; v0 < n; v0 += TW) {
-    for (int q = wave; q < TW && v0 + q < n; q += W) {
-      const int v = v0 + q;
-      int p0, dv;
-      var_range<DV>(g, v, p0, dv);
-      float ev[DMAX], pre[DMAX];
-      int eid[DMAX];
-      const float r = st.R[v * TW + lane];
-      const float L = var_posterior<DV>(r, Eb, g.var_edges, p0, dv, lane, ev, pre, eid);
-      stage[q][lane] = my_iters > 0 ? L : r;
-    }
-    __syncthreads();
-    for (int r = wave; r < nvalid; r += W) {
-      const int v = v0 + lane;
-      if (v < n) {
-        const float x = stage[lane][r];
-        const size_t off = (size_t)(cw0 + r) * (size_t)n + (size_t)v;
-        post[off] = x;
-        hard[off] = x <= 0.0f ? 1 : 0;
-      }
-    }
-    __syncthreads();
-  }
-}
 
 template <int DC, int DV>
 __global__ void __launch_bounds__(1024)
     plain_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
-                        int max_iters, int early_stop, float *wsE0, float *wsE1, float *wsM, float *wsR,
-                        unsigned long long *wsZ, uint8_t *__restrict__ hard, float *__restrict__ post,
+                        int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard, float *__restrict__ post,
                         int32_t *__restrict__ iters) {
   __shared__ float stage[TW][TW + 1];
   __shared__ unsigned long long unsat_w[16];
@@ -143,7 +36,7 @@ __global__ void __launch_bounds__(1024)
   const int tile = blockIdx.x;
   const int cw0 = tile * TW;
   const int nvalid = min(TW, B - cw0);
-  const TileState st = tile_state(wsE0, wsE1, wsM, wsR, wsZ, g, tile);
+  const TileState st = tile_state_block(ws + (size_t)tile * tile_bytes(g.nnz, g.n), g.nnz, g.n);
 
   ingest_tile<DV>(g, llr32, llr64, cw0, nvalid, st, stage, wave, W, lane);
 
@@ -186,29 +79,20 @@ using namespace ldpc;
 
 size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch) {
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
-  return 3 * align256(tiles * (size_t)g->nnz * TW * sizeof(float)) +
-         align256(tiles * (size_t)g->n * TW * sizeof(float)) + align256(tiles * (size_t)g->n * 8);
+  return tiles * tile_bytes(g->nnz, g->n);
 }
 
 namespace {
 
-using PlainKernel = void (*)(GraphDev, const float *, const double *, int, int, int, float *, float *, float *,
-                             float *, unsigned long long *, uint8_t *, float *, int32_t *);
+using PlainKernel = void (*)(GraphDev, const float *, const double *, int, int, int, char *, uint8_t *, float *,
+                             int32_t *);
 
-PlainKernel pick_plain(const ldpc_graph_s *g, const GraphDev &d) {
-#define LDPC_CASE(C, V) \
-  if (d.dc == C && d.dv == V) return plain_decode_kernel<C, V>;
-  LDPC_CASE(6, 3)
-  LDPC_CASE(4, 3)
-  LDPC_CASE(12, 3)
-  LDPC_CASE(15, 3)
-  LDPC_CASE(12, 6)
-  LDPC_CASE(12, 9)
-#undef LDPC_CASE
-  if (g->dc_max <= 8) return plain_decode_kernel<-8, -LDPC_MAX_VAR_DEGREE>;
-  if (g->dc_max <= 16) return plain_decode_kernel<-16, -LDPC_MAX_VAR_DEGREE>;
-  if (g->dc_max <= 24) return plain_decode_kernel<-24, -LDPC_MAX_VAR_DEGREE>;
-  return plain_decode_kernel<-LDPC_MAX_CHECK_DEGREE, -LDPC_MAX_VAR_DEGREE>;
+PlainKernel pick_plain(const ldpc_graph_s *g) {
+  PlainKernel k = nullptr;
+#define LDPC_PICK(C, V) k = plain_decode_kernel<C, V>
+  LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
+#undef LDPC_PICK
+  return k;
 }
 
 }  // namespace
@@ -219,20 +103,11 @@ ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr
   (void)ws_bytes;
   GraphDev d = graph_dev(g);
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
-  char *p = (char *)ws;
-  const size_t ebytes = align256(tiles * (size_t)g->nnz * TW * sizeof(float));
-  float *wsE0 = (float *)p;
-  float *wsE1 = (float *)(p + ebytes);
-  float *wsM = (float *)(p + 2 * ebytes);
-  p += 3 * ebytes;
-  float *wsR = (float *)p;
-  p += align256(tiles * (size_t)g->n * TW * sizeof(float));
-  unsigned long long *wsZ = (unsigned long long *)p;
-  PlainKernel k = pick_plain(g, d);
+  PlainKernel k = pick_plain(g);
   const float *l32 = llr_f64 ? nullptr : (const float *)llr;
   const double *l64 = llr_f64 ? (const double *)llr : nullptr;
   hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * waves), 0, stream, d, l32, l64, (int)batch, (int)max_iters,
-                     (int)(early_stop != 0), wsE0, wsE1, wsM, wsR, wsZ, hard, post, iters);
+                     (int)(early_stop != 0), (char *)ws, hard, post, iters);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;
 }

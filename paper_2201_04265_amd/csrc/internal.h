@@ -45,6 +45,54 @@ inline GraphDev graph_dev(const ldpc_graph_s *g) {
   return d;
 }
 
+// Degree specialisations compiled for the kernels: fixed (dc, dv) pairs, then
+// generic kernels for irregular codes up to a maximum check degree.
+enum KernelKind : int32_t {
+  KIND_6_3 = 0,
+  KIND_4_3,
+  KIND_12_3,
+  KIND_15_3,
+  KIND_12_6,
+  KIND_12_9,
+  KIND_G8,
+  KIND_G16,
+  KIND_G24,
+  KIND_G32,
+  KIND_COUNT
+};
+
+inline int32_t kernel_kind(const ldpc_graph_s *g) {
+  const bool reg = g->dc_min == g->dc_max && g->dv_min == g->dv_max;
+  if (reg) {
+    const int dc = g->dc_max, dv = g->dv_max;
+    if (dc == 6 && dv == 3) return KIND_6_3;
+    if (dc == 4 && dv == 3) return KIND_4_3;
+    if (dc == 12 && dv == 3) return KIND_12_3;
+    if (dc == 15 && dv == 3) return KIND_15_3;
+    if (dc == 12 && dv == 6) return KIND_12_6;
+    if (dc == 12 && dv == 9) return KIND_12_9;
+  }
+  if (g->dc_max <= 8) return KIND_G8;
+  if (g->dc_max <= 16) return KIND_G16;
+  if (g->dc_max <= 24) return KIND_G24;
+  return KIND_G32;
+}
+
+// Expands F(DC, DV) for the specialisation of `kind` (DC/DV < 0: generic up to -DC/-DV).
+#define LDPC_KIND_SWITCH(kind, F)                         \
+  switch (kind) {                                         \
+    case KIND_6_3: F(6, 3); break;                        \
+    case KIND_4_3: F(4, 3); break;                        \
+    case KIND_12_3: F(12, 3); break;                      \
+    case KIND_15_3: F(15, 3); break;                      \
+    case KIND_12_6: F(12, 6); break;                      \
+    case KIND_12_9: F(12, 9); break;                      \
+    case KIND_G8: F(-8, -LDPC_MAX_VAR_DEGREE); break;     \
+    case KIND_G16: F(-16, -LDPC_MAX_VAR_DEGREE); break;   \
+    case KIND_G24: F(-24, -LDPC_MAX_VAR_DEGREE); break;   \
+    default: F(-LDPC_MAX_CHECK_DEGREE, -LDPC_MAX_VAR_DEGREE); break; \
+  }
+
 // Error reporting: thread-local detail of the last failure.
 ldpc_status set_error(ldpc_status s, const std::string &msg);
 ldpc_status hip_error(hipError_t e, const char *what);

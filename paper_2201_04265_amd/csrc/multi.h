@@ -1,0 +1,37 @@
+// Batched persistent decoder: device job descriptors and host helpers.
+#pragma once
+
+#include "internal.h"
+
+// One code of a batched launch, passed by value in the kernel arguments.
+struct MultiJob {
+  GraphDev g;
+  const float *llr;
+  uint8_t *hard;
+  float *post;
+  int32_t *iters;
+  const int32_t *order;  // optional word order (NULL: 0..batch-1)
+  char *ws;              // nslots tile states of this code
+  int32_t batch, max_iters;
+  int32_t slot0, nslots;  // workgroups [slot0, slot0 + nslots) serve this code
+  int32_t kind;           // degree specialisation (KernelKind)
+  int32_t dc_max;         // largest check degree
+};
+
+struct MultiArgs {
+  MultiJob jobs[LDPC_MAX_CODES];
+  int32_t njobs;
+};
+
+using MultiKernel = void (*)(MultiArgs, int *, int);
+MultiKernel multi_kernel_for(const MultiArgs &a);
+
+// Validates the jobs, fills automatic slot counts and returns the workspace size.
+ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                          const ldpc_multi_shape *shape_in, ldpc_multi_shape *shape_out, size_t *ws_bytes);
+// Lays the jobs out over the workspace.
+ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs, const int32_t *const *orders,
+                       const ldpc_multi_shape &sh, void *ws, MultiArgs *a, int **counters, int *grid);
+// Enqueues the counter reset and the persistent launch.
+ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
+                          hipStream_t stream);

@@ -1,0 +1,296 @@
+// Batched persistent decoder: several codes, one launch, per-word refill.
+//
+// Sec. III-C distributes a batch of whole words over workers that decode them
+// one after another.  Here a worker is a "slot": one workgroup holding the
+// state of 64 words (one per lane) of a single code, with the same tile layout
+// and the same check / variable updates as the plain decoder.  A lane whose word
+// stops (zero syndrome or max_iters) writes that word's outputs and claims the
+// next word of its code from a per-code atomic counter (one atomic per
+// wavefront per refill), so no lane waits for the slowest word of a tile.  All
+// codes of a batch run in one launch: workgroup i serves the code whose slot
+// range contains i.  Per word the arithmetic and its order are those of the
+// plain decoder, so outputs are bit-identical to it whatever lane or slot ran
+// the word.
+//
+// Step G of a slot: check phase writes E into E[(G+1)&1] and tests the
+// syndrome of the decisions Z; lanes that stop at G have their last messages in
+// E[G&1] (all lanes of a slot share the step parity, so buffer choice is uniform).
+#include "internal.h"
+#include "multi.h"
+#include "tile.h"
+
+namespace ldpc {
+
+// Load fresh words into the lanes in `fresh_mask`: R, first messages M = clamp(R)
+// and their channel decisions in Z (other lanes' bits kept).
+template <int DV>
+__device__ __forceinline__ void ingest_lanes(const GraphDev &g, const float *__restrict__ llr, TileState st, int word,
+                                             bool fresh, unsigned long long fresh_mask, int wave, int W, int lane) {
+  for (int v = wave; v < g.n; v += W) {
+    float x = 0.0f;
+    if (fresh) {
+      x = llr[(size_t)word * (size_t)g.n + (size_t)v];
+      st.R[v * TW + lane] = x;
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      const float mx = clamp_msg(x);
+      for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
+    }
+    const unsigned long long zb = __ballot(x <= 0.0f) & fresh_mask;
+    if (lane == 0) st.Z[v] = (st.Z[v] & ~fresh_mask) | zb;
+  }
+}
+
+// Outputs of the stopped lanes: posterior from their last messages Ep (R if they
+// stopped before any iteration), decisions, straight into [B][n].
+template <int DV>
+__device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, const float *Ep, int word, int it_lane,
+                                             bool done, float *__restrict__ post, uint8_t *__restrict__ hard,
+                                             int wave, int W, int lane) {
+  constexpr int DMAX = DV > 0 ? DV : -DV;
+  for (int v = wave; v < g.n; v += W) {
+    int p0, dv;
+    var_range<DV>(g, v, p0, dv);
+    float ev[DMAX], pre[DMAX];
+    int eid[DMAX];
+    const float r = st.R[v * TW + lane];
+    const float L = var_posterior<DV>(r, Ep, g.var_edges, p0, dv, lane, ev, pre, eid);
+    if (done) {
+      const float x = it_lane > 0 ? L : r;
+      const size_t off = (size_t)word * (size_t)g.n + (size_t)v;
+      post[off] = x;
+      hard[off] = x <= 0.0f ? 1 : 0;
+    }
+  }
+}
+
+__device__ __forceinline__ int next_word(const MultiJob &J, int w) {
+  return w < J.batch ? (J.order ? J.order[w] : w) : -1;
+}
+
+template <int DC, int DV>
+__device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop,
+                         unsigned long long *unsat_w, int *lane_word, int wave, int W, int lane) {
+  const GraphDev &g = J.g;
+  const TileState st = tile_state_block(J.ws + (size_t)local_slot * tile_bytes(g.nnz, g.n), g.nnz, g.n);
+
+  if (wave == 0) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(counter, TW);
+    base = __shfl(base, 0);
+    lane_word[lane] = next_word(J, base + lane);
+  }
+  __syncthreads();
+  int word = lane_word[lane];
+  bool has = word >= 0;
+  int it_lane = 0;
+  const unsigned long long first = __ballot(has);
+  if (first == 0ull) return;  // uniform: nothing left for this slot
+  ingest_lanes<DV>(g, J.llr, st, word, has, first, wave, W, lane);
+  __syncthreads();
+
+  for (int G = 0;; ++G) {
+    float *En = ((G + 1) & 1) ? st.E1 : st.E0;
+    const float *Ep = (G & 1) ? st.E1 : st.E0;
+    int unsat = 0;
+    for (int c = wave; c < g.m; c += W) {
+      int e0, dc;
+      check_range<DC>(g, c, e0, dc);
+      unsat |= check_update<DC>(st.M, En, st.Z, g.col_idx, e0, dc, lane, has);
+    }
+    const unsigned long long b = __ballot(unsat);
+    if (lane == 0) unsat_w[wave] = b;
+    __syncthreads();
+    unsigned long long um = 0;
+    for (int w = 0; w < W; ++w) um |= unsat_w[w];
+    const bool lane_unsat = (um >> lane) & 1ull;
+    const bool done = has && ((early_stop && !lane_unsat) || it_lane == J.max_iters);
+    const bool running = has && !done;
+
+    for (int v = wave; v < g.n; v += W) {
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      var_update<DV>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running);
+    }
+
+    const unsigned long long done_mask = __ballot(done);
+    if (done_mask != 0ull) {  // same value in every wave
+      egress_lanes<DV>(g, st, Ep, word, it_lane, done, J.post, J.hard, wave, W, lane);
+      if (wave == 0) {
+        if (done) J.iters[word] = it_lane;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(counter, __popcll(done_mask));
+        base = __shfl(base, 0);
+        const int rank = __popcll(done_mask & ((1ull << lane) - 1ull));
+        lane_word[lane] = done ? next_word(J, base + rank) : word;
+      }
+      __syncthreads();
+      const int nw = lane_word[lane];
+      const bool fresh = done && nw >= 0;
+      const unsigned long long fmask = __ballot(fresh);
+      word = nw;
+      has = nw >= 0;
+      if (fmask != 0ull) ingest_lanes<DV>(g, J.llr, st, word, fresh, fmask, wave, W, lane);
+      if (fresh) it_lane = 0;
+    }
+    if (running) ++it_lane;
+    if (__ballot(has) == 0ull) break;  // same value in every wave
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int find_job(const MultiArgs &a, int slot) {
+  int q = 0;
+  for (int i = 0; i < a.njobs; ++i)
+    if (slot >= a.jobs[i].slot0) q = i;
+  return q;
+}
+
+template <int DC, int DV>
+__global__ void __launch_bounds__(1024) multi_kernel_single(MultiArgs a, int *counters, int early_stop) {
+  __shared__ unsigned long long unsat_w[16];
+  __shared__ int lane_word[TW];
+  const int slot = blockIdx.x;
+  const int q = find_job(a, slot);
+  run_slot<DC, DV>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, unsat_w, lane_word, wave_id(),
+                   blockDim.x >> 6, lane_id());
+}
+
+// Codes of different degree profiles in one launch: the generic (runtime degree)
+// path for every code, with the largest check degree of the batch as the bound.
+template <int DC>
+__global__ void __launch_bounds__(1024) multi_kernel_mixed(MultiArgs a, int *counters, int early_stop) {
+  __shared__ unsigned long long unsat_w[16];
+  __shared__ int lane_word[TW];
+  const int slot = blockIdx.x;
+  const int q = find_job(a, slot);
+  run_slot<DC, -LDPC_MAX_VAR_DEGREE>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, unsat_w,
+                                     lane_word, wave_id(), blockDim.x >> 6, lane_id());
+}
+
+__global__ void reset_counters(int *counters, int n) {
+  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
+}
+
+}  // namespace ldpc
+
+using namespace ldpc;
+
+namespace {
+
+using MultiKernel = void (*)(MultiArgs, int *, int);
+
+MultiKernel pick_single(int32_t kind) {
+  MultiKernel k = nullptr;
+#define LDPC_PICK(C, V) k = multi_kernel_single<C, V>
+  LDPC_KIND_SWITCH(kind, LDPC_PICK)
+#undef LDPC_PICK
+  return k;
+}
+
+}  // namespace
+
+MultiKernel multi_kernel_for(const MultiArgs &a) {
+  bool same = true;
+  int dcmax = 0;
+  for (int i = 0; i < a.njobs; ++i) {
+    same &= a.jobs[i].kind == a.jobs[0].kind;
+    dcmax = std::max(dcmax, a.jobs[i].dc_max);
+  }
+  if (same) return pick_single(a.jobs[0].kind);
+  if (dcmax <= 16) return multi_kernel_mixed<-16>;
+  if (dcmax <= 24) return multi_kernel_mixed<-24>;
+  return multi_kernel_mixed<-LDPC_MAX_CHECK_DEGREE>;
+}
+
+ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                          const ldpc_multi_shape *shape_in, ldpc_multi_shape *shape_out, size_t *ws_bytes) {
+  if (!graphs || !jobs || ncodes < 1 || ncodes > LDPC_MAX_CODES)
+    return set_error(LDPC_ERR_INVALID_ARG, "need 1.." + std::to_string(LDPC_MAX_CODES) + " codes");
+  ldpc_multi_shape sh{};
+  if (shape_in) sh = *shape_in;
+  if (sh.waves == 0) sh.waves = 16;
+  if (sh.waves < 1 || sh.waves > 16) return set_error(LDPC_ERR_INVALID_ARG, "waves must be in 1..16");
+  for (int q = 0; q < ncodes; ++q) {
+    if (!graphs[q]) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
+    if (jobs[q].batch < 0 || jobs[q].max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative batch/max_iters");
+    if (sh.slots[q] < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative slot count");
+  }
+  // automatic slot counts: fill the resident capacity, shared in proportion to words x edges
+  bool need_auto = false;
+  for (int q = 0; q < ncodes; ++q) need_auto |= sh.slots[q] == 0 && jobs[q].batch > 0;
+  if (need_auto) {
+    int dev = 0, cus = 0;
+    LDPC_HIP_CHECK(hipGetDevice(&dev));
+    LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MultiArgs probe{};
+    probe.njobs = ncodes;
+    for (int q = 0; q < ncodes; ++q) {
+      probe.jobs[q].kind = kernel_kind(graphs[q]);
+      probe.jobs[q].dc_max = graphs[q]->dc_max;
+    }
+    int per_cu = 0;
+    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)multi_kernel_for(probe),
+                                                                64 * sh.waves, 0));
+    const double cap = (double)cus * (per_cu > 0 ? per_cu : 1);
+    double total = 0;
+    for (int q = 0; q < ncodes; ++q) total += (double)jobs[q].batch * (double)graphs[q]->nnz;
+    for (int q = 0; q < ncodes; ++q) {
+      if (sh.slots[q] != 0 || jobs[q].batch == 0) continue;
+      const int tiles = (jobs[q].batch + TW - 1) / TW;
+      int s = (int)(cap * (double)jobs[q].batch * (double)graphs[q]->nnz / total + 0.5);
+      sh.slots[q] = std::max(1, std::min(s, tiles));
+    }
+  }
+  size_t bytes = 256;  // counters
+  for (int q = 0; q < ncodes; ++q) {
+    if (jobs[q].batch == 0) sh.slots[q] = 0;
+    bytes += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
+  }
+  if (shape_out) *shape_out = sh;
+  if (ws_bytes) *ws_bytes = bytes;
+  return LDPC_OK;
+}
+
+ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs, const int32_t *const *orders,
+                       const ldpc_multi_shape &sh, void *ws, MultiArgs *a, int **counters, int *grid) {
+  char *p = (char *)ws;
+  *counters = (int *)p;
+  p += 256;
+  a->njobs = ncodes;
+  int slot = 0;
+  for (int q = 0; q < ncodes; ++q) {
+    MultiJob &J = a->jobs[q];
+    const ldpc_job &j = jobs[q];
+    if (j.batch > 0 && (!j.llr || !j.hard_bits || !j.posterior || !j.iters_used))
+      return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer in job " + std::to_string(q));
+    J.g = graph_dev(graphs[q]);
+    J.llr = j.llr;
+    J.hard = j.hard_bits;
+    J.post = j.posterior;
+    J.iters = j.iters_used;
+    J.batch = j.batch;
+    J.max_iters = j.max_iters;
+    J.slot0 = slot;
+    J.nslots = sh.slots[q];
+    J.kind = kernel_kind(graphs[q]);
+    J.dc_max = graphs[q]->dc_max;
+    J.ws = p;
+    J.order = orders ? orders[q] : nullptr;
+    p += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
+    slot += sh.slots[q];
+  }
+  *grid = slot;
+  return LDPC_OK;
+}
+
+ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counters, a.njobs);
+  LDPC_HIP_CHECK(hipGetLastError());
+  if (grid == 0) return LDPC_OK;
+  hipLaunchKernelGGL(multi_kernel_for(a), dim3(grid), dim3(64 * waves), 0, stream, a, counters,
+                     (int)(early_stop != 0));
+  LDPC_HIP_CHECK(hipGetLastError());
+  return LDPC_OK;
+}

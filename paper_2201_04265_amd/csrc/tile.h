@@ -1,0 +1,128 @@
+// Tile state and per-tile data movement shared by the decoder kernels.
+#pragma once
+
+#include "internal.h"
+#include "spa_core.h"
+
+namespace ldpc {
+
+// HBM state of one 64-word tile (FP32 [index][64] unless noted):
+//   M  [nnz]  v->c messages (Eq. 6, clamped)       R [n]  channel LLRs (Eq. 4)
+//   E0/E1 [nnz] c->v messages of even / odd steps (Eq. 5)
+//   Z  [n] u64 decision masks, bit l = z_v of lane l's word (Eq. 8)
+struct TileState {
+  float *E0, *E1, *M, *R;
+  unsigned long long *Z;
+};
+
+// Bytes of one tile's state, each array 256-byte aligned.
+__host__ __device__ inline size_t tile_bytes(int64_t nnz, int32_t n) {
+  const size_t e = ((size_t)nnz * TW * sizeof(float) + 255) & ~size_t(255);
+  const size_t v = ((size_t)n * TW * sizeof(float) + 255) & ~size_t(255);
+  const size_t z = ((size_t)n * 8 + 255) & ~size_t(255);
+  return 3 * e + v + z;
+}
+
+// Tile state carved from one contiguous per-tile block.
+__device__ __forceinline__ TileState tile_state_block(char *base, int64_t nnz, int32_t n) {
+  const size_t e = ((size_t)nnz * TW * sizeof(float) + 255) & ~size_t(255);
+  const size_t v = ((size_t)n * TW * sizeof(float) + 255) & ~size_t(255);
+  TileState s;
+  s.E0 = (float *)base;
+  s.E1 = (float *)(base + e);
+  s.M = (float *)(base + 2 * e);
+  s.R = (float *)(base + 3 * e);
+  s.Z = (unsigned long long *)(base + 3 * e + v);
+  return s;
+}
+
+template <int DV>
+__device__ __forceinline__ void var_range(const GraphDev &g, int v, int &p0, int &dv) {
+  if (DV > 0) {
+    p0 = v * DV;
+    dv = DV;
+  } else {
+    p0 = g.var_ptr[v];
+    dv = g.var_ptr[v + 1] - p0;
+  }
+}
+
+template <int DC>
+__device__ __forceinline__ void check_range(const GraphDev &g, int c, int &e0, int &dc) {
+  if (DC > 0) {
+    e0 = c * DC;
+    dc = DC;
+  } else {
+    e0 = g.row_ptr[c];
+    dc = g.row_ptr[c + 1] - e0;
+  }
+}
+
+// [B][n] channel LLRs -> R of the tile (through 64 x 64 LDS blocks), the first
+// v->c messages M = clamp(R) on every edge, and the channel decisions Z.
+template <int DV>
+__device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__restrict__ llr32,
+                                            const double *__restrict__ llr64, int cw0, int nvalid, TileState st,
+                                            float (*stage)[TW + 1], int wave, int W, int lane) {
+  const int n = g.n;
+  for (int v0 = 0; v0 < n; v0 += TW) {
+    for (int r = wave; r < TW; r += W) {
+      float x = 0.0f;
+      const int v = v0 + lane;
+      if (r < nvalid && v < n) {
+        const size_t off = (size_t)(cw0 + r) * (size_t)n + (size_t)v;
+        x = llr64 ? (float)llr64[off] : llr32[off];
+      }
+      stage[r][lane] = x;
+    }
+    __syncthreads();
+    for (int q = wave; q < TW && v0 + q < n; q += W) {
+      const int v = v0 + q;
+      const float x = stage[lane][q];
+      st.R[v * TW + lane] = x;
+      const unsigned long long z = __ballot(x <= 0.0f);
+      if (lane == 0) st.Z[v] = z;
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      const float mx = clamp_msg(x);
+      for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
+    }
+    __syncthreads();
+  }
+}
+
+// Final posterior of each lane's word from its own E buffer -> post and hard [B][n].
+template <int DV>
+__device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int my_iters, int cw0, int nvalid,
+                                            float *__restrict__ post, uint8_t *__restrict__ hard,
+                                            float (*stage)[TW + 1], int wave, int W, int lane) {
+  constexpr int DMAX = DV > 0 ? DV : -DV;
+  const int n = g.n;
+  const float *Eb = (my_iters & 1) ? st.E1 : st.E0;
+  for (int v0 = 0; v0 < n; v0 += TW) {
+    for (int q = wave; q < TW && v0 + q < n; q += W) {
+      const int v = v0 + q;
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      float ev[DMAX], pre[DMAX];
+      int eid[DMAX];
+      const float r = st.R[v * TW + lane];
+      const float L = var_posterior<DV>(r, Eb, g.var_edges, p0, dv, lane, ev, pre, eid);
+      stage[q][lane] = my_iters > 0 ? L : r;
+    }
+    __syncthreads();
+    for (int r = wave; r < nvalid; r += W) {
+      const int v = v0 + lane;
+      if (v < n) {
+        const float x = stage[lane][r];
+        const size_t off = (size_t)(cw0 + r) * (size_t)n + (size_t)v;
+        post[off] = x;
+        hard[off] = x <= 0.0f ? 1 : 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+
+}  // namespace ldpc
