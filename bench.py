@@ -3,14 +3,19 @@
 Workload (one "step"): the Eb/N0 sweep {1.0, 1.5, 2.0, 2.5, 3.0} dB of a seeded
 (3,6)-regular n=4096 code without 4-cycles, 65536 codewords per point (random
 information bits, systematic encoding, BPSK/AWGN, FP32 LLRs), at most 50
-iterations with per-word syndrome early stop.  All inputs are resident in HBM
-before timing starts.
+iterations with per-word syndrome early stop.  The five points form one batch of
+327680 words, resident in HBM before timing starts.
 
-Reported (one JSON line): coded Gbit/s of the step (value), edge updates/s
-(useful iterations only), per-point iterations/BER/FER, the roofline of the
-decode kernel (algorithmic HBM bytes of the useful iterations / average launch
-duration from HIP events on the launch stream), and the FP64 CPU oracle timed on
-a bounded sample of the same words.
+Two forms decode the same batch:
+  plain    one ldpc_decode launch (64-word tiles, each runs until its slowest word)
+  batched  one ldpc_decode_multi persistent launch with per-word refill, launch
+           shape from the autotuner (cached per code / batch / architecture)
+`value` is the batched form's coded Gbit/s; both forms are reported.
+
+Also reported: edge updates/s (useful iterations only), per-point iterations /
+BER / FER, the roofline of the batched kernel (algorithmic HBM bytes of the
+useful iterations / average launch duration from HIP events on the launch
+stream), and the FP64 CPU oracle timed on a bounded sample of the same words.
 """
 from __future__ import annotations
 
@@ -27,61 +32,101 @@ if ROOT not in sys.path:
 
 METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batched"
 HBM_PEAK_GBS = 8000.0
+MAX_ITERS = 50
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def plain_bytes_per_word_iter(n: int, E: int) -> int:
-    """HBM bytes one codeword moves per flooding iteration in the plain kernel's layout.
-
-    check phase: read old c->v message and the gathered posterior per edge, write
-    the new message (12 B/edge); variable phase: read every message once and the
-    channel LLR, write the posterior (4 B/edge + 8 B/variable).
-    """
+def bytes_per_word_iteration(n: int, E: int) -> int:
+    """Algorithmic HBM bytes of one flooding iteration of one word with FP32 messages in HBM:
+    each half-iteration reads and writes one 4-byte message per edge (16 B/edge), and the
+    variable half reads the channel LLR and writes the posterior (8 B/variable)."""
     return 16 * E + 8 * n
 
 
-def make_inputs(args, torch):
-    import numpy as np
+def io_bytes_per_word(n: int) -> int:
+    """Channel LLRs in (4 B/bit), posterior (4 B/bit) and hard decision (1 B/bit) out."""
+    return 9 * n
 
+
+def make_inputs(args, torch):
     from synth import workloads as W
 
     code = W.code("c2")
     B = args.batch
     ebn0s = W.C2["ebn0s"]
-    llrs, cws = [], []
+    llr = torch.empty((B * len(ebn0s), code.n), dtype=torch.float32, device="cuda")
+    cw = torch.empty((B * len(ebn0s), code.n), dtype=torch.uint8, device="cuda")
     for key, e in enumerate(ebn0s):
         t0 = time.time()
         wd = W.words("c2", 2, key, e, 0, B, fp32=True)
-        llrs.append(torch.from_numpy(wd.llr).cuda())
-        cws.append(torch.from_numpy(wd.cw).cuda())
+        llr[key * B:(key + 1) * B].copy_(torch.from_numpy(wd.llr))
+        cw[key * B:(key + 1) * B].copy_(torch.from_numpy(wd.cw))
         log(f"[bench] inputs Eb/N0={e} dB: {B} words generated in {time.time() - t0:.1f}s")
         del wd
-    return code, ebn0s, llrs, cws, np
+    return code, ebn0s, llr, cw
 
 
-def cpu_baseline(code, ebn0s, B, sample, torch_llrs):
-    import numpy as np
-
+def cpu_baseline(code, ebn0s, sample):
     import oracle
     from synth import workloads as W
 
     threads = oracle.default_threads()
     words = 0
+    iters = 0
     t_total = 0.0
     for key, e in enumerate(ebn0s):
         llr = W.words("c2", 2, key, e, 0, sample, fp32=True).llr
         t0 = time.perf_counter()
-        oracle.decode(code, llr, 50, True, threads)
+        _, _, it, _ = oracle.decode(code, llr, MAX_ITERS, True, threads)
         t_total += time.perf_counter() - t0
         words += sample
-    gbps = words * code.n / t_total / 1e9
-    return {"value": gbps, "unit": "coded Gbit/s", "cores": threads, "kind": "oracle",
+        iters += int(it.sum())
+    return {"value": words * code.n / t_total / 1e9, "unit": "coded Gbit/s", "cores": threads, "kind": "oracle",
+            "edge_updates_per_s": iters * code.nnz / t_total,
             "sample": f"first {sample} words of each of the {len(ebn0s)} Eb/N0 points ({words} words), "
-                      f"FP64 C oracle, max 50 iterations, early stop; {t_total:.1f}s",
+                      f"FP64 C oracle, max {MAX_ITERS} iterations, early stop, {threads} threads; {t_total:.1f}s",
             "cpu": platform.processor() or platform.machine()}
+
+
+def time_launches(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def summarize(torch, name, ms, outs, cw, ebn0s, B, code, extra):
+    hard, post, iters = outs
+    it = iters.to(torch.int64)
+    useful = int(it.sum().item())
+    n, E = code.n, code.nnz
+    per_point = []
+    for i, e in enumerate(ebn0s):
+        sl = slice(i * B, (i + 1) * B)
+        errs = hard[sl] != cw[sl]
+        per_point.append({"ebn0_db": e, "mean_iters": float(it[sl].float().mean().item()),
+                          "words_at_max_iters": int((it[sl] == MAX_ITERS).sum().item()),
+                          "ber_coded": float(errs.float().mean().item()),
+                          "fer": float(errs.any(dim=1).float().mean().item())})
+    avg = sum(ms) / len(ms)
+    words = it.numel()
+    d = {"form": name, "ms_per_step": avg, "coded_gbit_s": words * n / (avg * 1e-3) / 1e9,
+         "edge_updates_per_s": useful * E / (avg * 1e-3), "useful_word_iterations": useful,
+         "alg_bytes_per_launch": useful * bytes_per_word_iteration(n, E) + words * io_bytes_per_word(n),
+         "per_point": per_point}
+    d["achieved_gb_s"] = d["alg_bytes_per_launch"] / (avg * 1e-3) / 1e9
+    d.update(extra)
+    return d
 
 
 def main():
@@ -89,8 +134,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=65536)
-    ap.add_argument("--waves", type=int, default=None)
+    ap.add_argument("--batch", type=int, default=65536, help="words per Eb/N0 point")
+    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--no-autotune", action="store_true", help="batched form with the library's default shape")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -98,8 +144,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this decoder runs on one GPU; multi-GPU runs are not supported",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this decoder runs on one GPU; runs on several GPUs are not supported "
+                                   "(codewords shard trivially, see the design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -115,89 +161,75 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
         return
 
-    code, ebn0s, llrs, cws, np = make_inputs(args, torch)
+    code, ebn0s, llr, cw = make_inputs(args, torch)
     B = args.batch
     g = P.Graph.from_code(code)
-    E, n = code.nnz, code.n
-    ws = torch.empty(P.workspace_size(g, B), dtype=torch.uint8, device="cuda")
-    outs = [(torch.empty((B, n), dtype=torch.uint8, device="cuda"),
-             torch.empty((B, n), dtype=torch.float32, device="cuda"),
-             torch.empty((B,), dtype=torch.int32, device="cuda")) for _ in ebn0s]
     stream = torch.cuda.current_stream()
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
 
-    def step(events=None):
-        for i in range(len(ebn0s)):
-            if events is not None:
-                events[i][0].record(stream)
-            P.decode(g, llrs[i], 50, True, waves=args.waves, workspace=ws, out=outs[i])
-            if events is not None:
-                events[i][1].record(stream)
+    if "plain" in forms:
+        ws = torch.empty(P.workspace_size(g, llr.shape[0]), dtype=torch.uint8, device="cuda")
+        outs = (torch.empty(llr.shape, dtype=torch.uint8, device="cuda"),
+                torch.empty(llr.shape, dtype=torch.float32, device="cuda"),
+                torch.empty((llr.shape[0],), dtype=torch.int32, device="cuda"))
+        ms = time_launches(torch, lambda: P.decode(g, llr, MAX_ITERS, True, workspace=ws, out=outs),
+                           args.steps, args.warmup, stream)
+        results["plain"] = summarize(torch, "plain", ms, outs, cw, ebn0s, B, code,
+                                     {"kernel": "plain_decode_kernel<6,3>", "waves": 8})
+        log(f"[bench] plain: {results['plain']['ms_per_step']:.1f} ms/step")
+        plain_outs = outs
+        del ws
+        torch.cuda.empty_cache()
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
+    if "batched" in forms:
+        batch = P.Batch([g], [llr], MAX_ITERS)
+        if args.no_autotune:
+            shape = P.Shape.make()
+        else:
+            t0 = time.time()
+            shape = P.tuned_shape(batch, True)
+            log(f"[bench] autotuned shape {shape.as_dict(1)} in {time.time() - t0:.1f}s")
+        resolved, _ = batch.resolve(shape)
+        ws = batch.workspace(shape)
+        ms = time_launches(torch, lambda: batch.run(True, shape, ws), args.steps, args.warmup, stream)
+        results["batched"] = summarize(torch, "batched", ms, batch.outs[0], cw, ebn0s, B, code,
+                                       {"kernel": "multi_kernel_single<6,3>", "shape": resolved.as_dict(1)})
+        log(f"[bench] batched: {results['batched']['ms_per_step']:.1f} ms/step")
+        if "plain" in results:
+            results["batched"]["bitwise_equal_to_plain"] = all(
+                bool(torch.equal(a, b)) for a, b in zip(batch.outs[0], plain_outs))
 
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in ebn0s]
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(ev[s])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in ev[s]] for s in range(args.steps)])
-    log(f"[bench] timed {args.steps} steps in {wall:.2f}s")
-
-    # statistics of the last step's outputs (identical every step: the decode is deterministic)
-    per_point = []
-    useful_iters = 0
-    for i, e in enumerate(ebn0s):
-        hard, post, iters = outs[i]
-        it = iters.to(torch.int64)
-        useful_iters += int(it.sum().item())
-        errs = (hard != cws[i])
-        per_point.append({"ebn0_db": e, "mean_iters": float(it.float().mean().item()),
-                          "max_iters_hit": int((it == 50).sum().item()),
-                          "ber_coded": float(errs.float().mean().item()),
-                          "fer": float(errs.any(dim=1).float().mean().item()),
-                          "ms": float(launch_ms[:, i].mean())})
-    step_ms = float(launch_ms.sum(axis=1).mean())
-    words = B * len(ebn0s)
-    gbps = words * n / (step_ms * 1e-3) / 1e9
-    edge_ups = useful_iters * E / (step_ms * 1e-3)
-    bpi = plain_bytes_per_word_iter(n, E)
-    avg_launch_ms = float(launch_ms.mean())
-    alg_bytes_per_launch = useful_iters * bpi / len(ebn0s) + words / len(ebn0s) * 9 * n  # + LLR in, post+hard out
-    achieved = alg_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-
+    head = results.get("batched") or results["plain"]
     result = {
         "metric": METRIC,
-        "value": gbps,
+        "value": head["coded_gbit_s"],
         "unit": "coded Gbit/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": step_ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "(3,6)-regular n=4096 m=2048 girth>=6, 65536 words x Eb/N0 {1.0,1.5,2.0,2.5,3.0} dB, "
-                               "max 50 iterations, syndrome early stop",
-                   "form": "plain", "batch_per_point": B, "edges": E},
-        "edge_updates_per_s": edge_ups,
-        "per_point": per_point,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "plain_decode_kernel<6,3>", "avg_launch_ms": avg_launch_ms,
-                     "alg_bytes_per_launch": alg_bytes_per_launch,
-                     "bytes_per_word_iteration": bpi},
+        "config": {"workload": "(3,6)-regular n=4096 m=2048 girth>=6 code; 65536 words at each Eb/N0 in "
+                               "{1.0,1.5,2.0,2.5,3.0} dB as one 327680-word batch; max 50 iterations, "
+                               "syndrome early stop",
+                   "form": head["form"], "words_per_step": int(llr.shape[0]), "edges": code.nnz},
+        "edge_updates_per_s": head["edge_updates_per_s"],
+        "forms": results,
+        "roofline": {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["achieved_gb_s"] / HBM_PEAK_GBS, "traffic": None, "kernel": head["kernel"],
+                     "avg_launch_ms": head["ms_per_step"], "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+                     "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
+                     "unit_of_work": "useful word-iteration (sum of iterations used over words) plus LLR "
+                                     "in / posterior and decisions out per word"},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(code, ebn0s, B, args.cpu_sample, llrs)
+        result["cpu_baseline"] = cpu_baseline(code, ebn0s, args.cpu_sample)
     print(json.dumps(result), flush=True)
 
 

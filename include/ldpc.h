@@ -123,12 +123,15 @@ typedef struct {
   int32_t *iters_used;/* [batch] out */
 } ldpc_job;
 
-/* Launch shape of a batched decode: waves per workgroup (0 = 16) and 64-word
- * slots (workgroups) per code (0 = automatic: the resident capacity of the GPU
- * shared in proportion to words x edges, at most one slot per 64 words). */
+/* Launch shape of a batched decode: waves per workgroup (0 = 8); 64-word slots
+ * (workgroups) per code (0 = automatic: the resident capacity of the GPU shared
+ * in proportion to words x edges, at most one slot per 64 words); refill: a slot
+ * writes out and replaces its stopped words once this many of its 64 lanes wait
+ * (0 = 1), or when none is still running. */
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];
+  int32_t refill;
 } ldpc_multi_shape;
 
 /* Shape ldpc_decode_multi would use (automatic slot counts filled in) and its workspace size. */

@@ -21,6 +21,7 @@ struct MultiJob {
 struct MultiArgs {
   MultiJob jobs[LDPC_MAX_CODES];
   int32_t njobs;
+  int32_t refill_min;  // pending lanes that trigger a refill
 };
 
 using MultiKernel = void (*)(MultiArgs, int *, int);

@@ -21,46 +21,27 @@
 
 namespace ldpc {
 
-// Load fresh words into the lanes in `fresh_mask`: R, first messages M = clamp(R)
-// and their channel decisions in Z (other lanes' bits kept).
-template <int DV>
+// Channel LLRs of fresh words into R (the variable phase then derives their first
+// messages and decisions with all incoming messages taken as 0).
 __device__ __forceinline__ void ingest_lanes(const GraphDev &g, const float *__restrict__ llr, TileState st, int word,
-                                             bool fresh, unsigned long long fresh_mask, int wave, int W, int lane) {
-  for (int v = wave; v < g.n; v += W) {
-    float x = 0.0f;
-    if (fresh) {
-      x = llr[(size_t)word * (size_t)g.n + (size_t)v];
-      st.R[v * TW + lane] = x;
-      int p0, dv;
-      var_range<DV>(g, v, p0, dv);
-      const float mx = clamp_msg(x);
-      for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
-    }
-    const unsigned long long zb = __ballot(x <= 0.0f) & fresh_mask;
-    if (lane == 0) st.Z[v] = (st.Z[v] & ~fresh_mask) | zb;
-  }
+                                             bool fresh, int wave, int W, int lane) {
+  if (!fresh) return;
+  const float *src = llr + (size_t)word * (size_t)g.n;
+  for (int v = wave; v < g.n; v += W) st.R[v * TW + lane] = src[v];
 }
 
-// Outputs of the stopped lanes: posterior from their last messages Ep (R if they
-// stopped before any iteration), decisions, straight into [B][n].
-template <int DV>
-__device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, const float *Ep, int word, int it_lane,
-                                             bool done, float *__restrict__ post, uint8_t *__restrict__ hard,
-                                             int wave, int W, int lane) {
-  constexpr int DMAX = DV > 0 ? DV : -DV;
+// Outputs of the lanes in `out`: their last posterior (kept in L by the variable
+// phase) and its decisions, straight into the word's row of [B][n].
+__device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, int word, bool out,
+                                             float *__restrict__ post, uint8_t *__restrict__ hard, int wave, int W,
+                                             int lane) {
+  if (!out) return;
+  float *prow = post + (size_t)word * (size_t)g.n;
+  uint8_t *hrow = hard + (size_t)word * (size_t)g.n;
   for (int v = wave; v < g.n; v += W) {
-    int p0, dv;
-    var_range<DV>(g, v, p0, dv);
-    float ev[DMAX], pre[DMAX];
-    int eid[DMAX];
-    const float r = st.R[v * TW + lane];
-    const float L = var_posterior<DV>(r, Ep, g.var_edges, p0, dv, lane, ev, pre, eid);
-    if (done) {
-      const float x = it_lane > 0 ? L : r;
-      const size_t off = (size_t)word * (size_t)g.n + (size_t)v;
-      post[off] = x;
-      hard[off] = x <= 0.0f ? 1 : 0;
-    }
+    const float x = st.L[v * TW + lane];
+    prow[v] = x;
+    hrow[v] = x <= 0.0f ? 1 : 0;
   }
 }
 
@@ -68,11 +49,25 @@ __device__ __forceinline__ int next_word(const MultiJob &J, int w) {
   return w < J.batch ? (J.order ? J.order[w] : w) : -1;
 }
 
+// Variable phase of a slot: running lanes update, fresh lanes initialise.
+template <int DV>
+__device__ __forceinline__ void slot_var_phase(const GraphDev &g, TileState st, const float *En, bool running,
+                                               bool fresh, int wave, int W, int lane) {
+  for (int v = wave; v < g.n; v += W) {
+    int p0, dv;
+    var_range<DV>(g, v, p0, dv);
+    var_update<DV, true>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running || fresh, fresh, st.L);
+  }
+}
+
+// One slot: lanes take words of job J until its queue is empty.  A lane whose
+// word stops becomes pending; pending lanes are written out and refilled together
+// once at least `refill_min` of them wait or no lane is running.
 template <int DC, int DV>
-__device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop,
+__device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop, int refill_min,
                          unsigned long long *unsat_w, int *lane_word, int wave, int W, int lane) {
   const GraphDev &g = J.g;
-  const TileState st = tile_state_block(J.ws + (size_t)local_slot * tile_bytes(g.nnz, g.n), g.nnz, g.n);
+  const TileState st = tile_state_block(J.ws + (size_t)local_slot * slot_bytes(g.nnz, g.n), g.nnz, g.n);
 
   if (wave == 0) {
     int base = 0;
@@ -82,21 +77,22 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
   }
   __syncthreads();
   int word = lane_word[lane];
-  bool has = word >= 0;
+  bool has = word >= 0;  // lane holds a word (running or pending)
+  bool pending = false;  // its word has stopped and waits for output
   int it_lane = 0;
-  const unsigned long long first = __ballot(has);
-  if (first == 0ull) return;  // uniform: nothing left for this slot
-  ingest_lanes<DV>(g, J.llr, st, word, has, first, wave, W, lane);
+  if (__ballot(has) == 0ull) return;  // uniform: nothing left for this slot
+  ingest_lanes(g, J.llr, st, word, has, wave, W, lane);
+  slot_var_phase<DV>(g, st, st.E0, false, has, wave, W, lane);
   __syncthreads();
 
   for (int G = 0;; ++G) {
     float *En = ((G + 1) & 1) ? st.E1 : st.E0;
-    const float *Ep = (G & 1) ? st.E1 : st.E0;
+    const bool active = has && !pending;
     int unsat = 0;
     for (int c = wave; c < g.m; c += W) {
       int e0, dc;
       check_range<DC>(g, c, e0, dc);
-      unsat |= check_update<DC>(st.M, En, st.Z, g.col_idx, e0, dc, lane, has);
+      unsat |= check_update<DC>(st.M, En, st.Z, g.col_idx, e0, dc, lane, active);
     }
     const unsigned long long b = __ballot(unsat);
     if (lane == 0) unsat_w[wave] = b;
@@ -104,37 +100,36 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
     unsigned long long um = 0;
     for (int w = 0; w < W; ++w) um |= unsat_w[w];
     const bool lane_unsat = (um >> lane) & 1ull;
-    const bool done = has && ((early_stop && !lane_unsat) || it_lane == J.max_iters);
-    const bool running = has && !done;
-
-    for (int v = wave; v < g.n; v += W) {
-      int p0, dv;
-      var_range<DV>(g, v, p0, dv);
-      var_update<DV>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running);
-    }
-
-    const unsigned long long done_mask = __ballot(done);
-    if (done_mask != 0ull) {  // same value in every wave
-      egress_lanes<DV>(g, st, Ep, word, it_lane, done, J.post, J.hard, wave, W, lane);
+    const bool stop = active && ((early_stop && !lane_unsat) || it_lane == J.max_iters);
+    pending = pending || stop;
+    const bool running = active && !stop;
+    const unsigned long long pmask = __ballot(pending);
+    const unsigned long long rmask = __ballot(running);
+    bool fresh = false;
+    if (pmask != 0ull && (__popcll(pmask) >= refill_min || rmask == 0ull)) {  // same in every wave
+      egress_lanes(g, st, word, pending, J.post, J.hard, wave, W, lane);
       if (wave == 0) {
-        if (done) J.iters[word] = it_lane;
+        if (pending) J.iters[word] = it_lane;
         int base = 0;
-        if (lane == 0) base = atomicAdd(counter, __popcll(done_mask));
+        if (lane == 0) base = atomicAdd(counter, __popcll(pmask));
         base = __shfl(base, 0);
-        const int rank = __popcll(done_mask & ((1ull << lane) - 1ull));
-        lane_word[lane] = done ? next_word(J, base + rank) : word;
+        const int rank = __popcll(pmask & ((1ull << lane) - 1ull));
+        lane_word[lane] = pending ? next_word(J, base + rank) : word;
       }
       __syncthreads();
       const int nw = lane_word[lane];
-      const bool fresh = done && nw >= 0;
-      const unsigned long long fmask = __ballot(fresh);
-      word = nw;
-      has = nw >= 0;
-      if (fmask != 0ull) ingest_lanes<DV>(g, J.llr, st, word, fresh, fmask, wave, W, lane);
-      if (fresh) it_lane = 0;
+      fresh = pending && nw >= 0;
+      if (pending) {
+        word = nw;
+        has = nw >= 0;
+        it_lane = 0;
+        pending = false;
+      }
+      ingest_lanes(g, J.llr, st, word, fresh, wave, W, lane);
     }
-    if (running) ++it_lane;
     if (__ballot(has) == 0ull) break;  // same value in every wave
+    slot_var_phase<DV>(g, st, En, running, fresh, wave, W, lane);
+    if (running) ++it_lane;
     __syncthreads();
   }
 }
@@ -152,8 +147,8 @@ __global__ void __launch_bounds__(1024) multi_kernel_single(MultiArgs a, int *co
   __shared__ int lane_word[TW];
   const int slot = blockIdx.x;
   const int q = find_job(a, slot);
-  run_slot<DC, DV>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, unsat_w, lane_word, wave_id(),
-                   blockDim.x >> 6, lane_id());
+  run_slot<DC, DV>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, a.refill_min, unsat_w, lane_word,
+                   wave_id(), blockDim.x >> 6, lane_id());
 }
 
 // Codes of different degree profiles in one launch: the generic (runtime degree)
@@ -164,8 +159,8 @@ __global__ void __launch_bounds__(1024) multi_kernel_mixed(MultiArgs a, int *cou
   __shared__ int lane_word[TW];
   const int slot = blockIdx.x;
   const int q = find_job(a, slot);
-  run_slot<DC, -LDPC_MAX_VAR_DEGREE>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, unsat_w,
-                                     lane_word, wave_id(), blockDim.x >> 6, lane_id());
+  run_slot<DC, -LDPC_MAX_VAR_DEGREE>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, a.refill_min,
+                                     unsat_w, lane_word, wave_id(), blockDim.x >> 6, lane_id());
 }
 
 __global__ void reset_counters(int *counters, int n) {
@@ -209,8 +204,10 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     return set_error(LDPC_ERR_INVALID_ARG, "need 1.." + std::to_string(LDPC_MAX_CODES) + " codes");
   ldpc_multi_shape sh{};
   if (shape_in) sh = *shape_in;
-  if (sh.waves == 0) sh.waves = 16;
+  if (sh.waves == 0) sh.waves = 8;
   if (sh.waves < 1 || sh.waves > 16) return set_error(LDPC_ERR_INVALID_ARG, "waves must be in 1..16");
+  if (sh.refill == 0) sh.refill = 1;
+  if (sh.refill < 1 || sh.refill > kTile) return set_error(LDPC_ERR_INVALID_ARG, "refill must be in 1..64");
   for (int q = 0; q < ncodes; ++q) {
     if (!graphs[q]) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
     if (jobs[q].batch < 0 || jobs[q].max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative batch/max_iters");
@@ -245,7 +242,7 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
   size_t bytes = 256;  // counters
   for (int q = 0; q < ncodes; ++q) {
     if (jobs[q].batch == 0) sh.slots[q] = 0;
-    bytes += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
+    bytes += (size_t)sh.slots[q] * slot_bytes(graphs[q]->nnz, graphs[q]->n);
   }
   if (shape_out) *shape_out = sh;
   if (ws_bytes) *ws_bytes = bytes;
@@ -258,6 +255,7 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
   *counters = (int *)p;
   p += 256;
   a->njobs = ncodes;
+  a->refill_min = sh.refill;
   int slot = 0;
   for (int q = 0; q < ncodes; ++q) {
     MultiJob &J = a->jobs[q];
@@ -277,7 +275,7 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
     J.dc_max = graphs[q]->dc_max;
     J.ws = p;
     J.order = orders ? orders[q] : nullptr;
-    p += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
+    p += (size_t)sh.slots[q] * slot_bytes(graphs[q]->nnz, graphs[q]->n);
     slot += sh.slots[q];
   }
   *grid = slot;

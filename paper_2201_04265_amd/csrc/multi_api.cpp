@@ -94,27 +94,31 @@ extern "C" ldpc_status ldpc_plan_destroy(ldpc_plan_t plan) {
   return LDPC_OK;
 }
 
-// Candidate shapes: waves per workgroup x a scale of the automatic slot counts.
+// Candidate shapes: waves per workgroup x a scale of the automatic slot counts x refill threshold.
 extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                            const int32_t *const *orders, int32_t early_stop, hipStream_t stream,
                                            ldpc_multi_shape *best, float *best_ms) {
   if (!best) return set_error(LDPC_ERR_INVALID_ARG, "best is NULL");
   std::vector<ldpc_multi_shape> cands;
-  for (int waves : {4, 8, 16}) {
+  for (int waves : {8, 16}) {
     ldpc_multi_shape base{};
     base.waves = waves;
     ldpc_multi_shape autos{};
     ldpc_status st = multi_resolve(graphs, ncodes, jobs, &base, &autos, nullptr);
     if (st != LDPC_OK) return st;
     for (double scale : {0.5, 1.0, 2.0}) {
-      ldpc_multi_shape c = autos;
-      for (int q = 0; q < ncodes; ++q) {
-        const int tiles = (jobs[q].batch + kTile - 1) / kTile;
-        c.slots[q] = jobs[q].batch ? std::max(1, std::min(tiles, (int)(autos.slots[q] * scale + 0.5))) : 0;
+      for (int refill : {1, 4}) {
+        ldpc_multi_shape c = autos;
+        c.refill = refill;
+        for (int q = 0; q < ncodes; ++q) {
+          const int tiles = (jobs[q].batch + kTile - 1) / kTile;
+          c.slots[q] = jobs[q].batch ? std::max(1, std::min(tiles, (int)(autos.slots[q] * scale + 0.5))) : 0;
+        }
+        bool dup = false;
+        for (auto &o : cands)
+          dup |= std::equal(o.slots, o.slots + ncodes, c.slots) && o.waves == c.waves && o.refill == c.refill;
+        if (!dup) cands.push_back(c);
       }
-      bool dup = false;
-      for (auto &o : cands) dup |= std::equal(o.slots, o.slots + ncodes, c.slots) && o.waves == c.waves;
-      if (!dup) cands.push_back(c);
     }
   }
   size_t need = 0;

@@ -21,18 +21,19 @@ class Job(ctypes.Structure):
 
 
 class Shape(ctypes.Structure):
-    _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES)]
+    _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32)]
 
     @classmethod
-    def make(cls, waves=0, slots=None):
+    def make(cls, waves=0, slots=None, refill=0):
         s = cls()
         s.waves = int(waves)
+        s.refill = int(refill)
         for i, v in enumerate(slots or []):
             s.slots[i] = int(v)
         return s
 
     def as_dict(self, ncodes):
-        return {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)]}
+        return {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill}
 
 
 class Batch:
@@ -165,7 +166,7 @@ def tuned_shape(batch: Batch, early_stop=True, retune=False) -> Shape:
             cache = {}
     if key in cache and not retune:
         d = cache[key]
-        return Shape.make(d["waves"], d["slots"])
+        return Shape.make(d["waves"], d["slots"], d.get("refill", 0))
     best, ms = batch.autotune(early_stop)
     cache[key] = dict(best.as_dict(batch.ncodes), ms=ms)
     try:
