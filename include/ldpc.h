@@ -173,6 +173,35 @@ ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, cons
                                 const int32_t *const *orders, int32_t early_stop, hipStream_t stream,
                                 ldpc_multi_shape *best, float *best_ms);
 
+/* ---- differentiable form --------------------------------------------------- */
+
+/*
+ * Unrolled flooding decoder with a weight on every c->v message where it enters a
+ * variable-node sum (Eqs. 5-7 with weights; T iterations, no early stop):
+ *   A^(1)_e = R_v,  E^(t) = Eq. 5 on clamp(A^(t)),
+ *   A^(t+1)_e = R_v + sum_{e' in N(v), e' != e} w[t-1][e'] E^(t)_e',
+ *   L_v = R_v + sum_{e in N(v)} w[T-1][e] E^(T)_e.
+ * All weights 1 gives ldpc_decode(early_stop = 0, max_iters = T) bit for bit.
+ * Sizes: checkpoints (the A^(t) of every iteration, kept between forward and
+ * backward), forward and backward workspaces, all device bytes.
+ */
+ldpc_status ldpc_unrolled_sizes(ldpc_graph_t g, int32_t batch, int32_t T, size_t *ckpt_bytes, size_t *fwd_ws_bytes,
+                                size_t *bwd_ws_bytes);
+
+/* llr [batch][n], w [T][edges] (edge order of ldpc_graph_edges), posterior [batch][n] out,
+ * ckpt written (caller-owned, 256-byte aligned); all device, FP32. */
+ldpc_status ldpc_unrolled_forward(ldpc_graph_t g, const float *llr, const float *w, int32_t batch, int32_t T,
+                                  float *posterior, void *ckpt, size_t ckpt_bytes, void *workspace, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* Adjoint of ldpc_unrolled_forward: given d loss / d posterior [batch][n] and the
+ * forward's checkpoints (unchanged), writes d loss / d llr [batch][n] and
+ * d loss / d w [T][edges] (summed over the batch in a fixed order; deterministic).
+ * Check-node messages are recomputed from the checkpoints. */
+ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, const void *ckpt, size_t ckpt_bytes,
+                                   const float *grad_post, int32_t batch, int32_t T, float *grad_llr, float *grad_w,
+                                   void *workspace, size_t ws_bytes, hipStream_t stream);
+
 const char *ldpc_status_string(ldpc_status s);
 const char *ldpc_last_error(void);
 

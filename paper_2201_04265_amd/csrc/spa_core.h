@@ -58,29 +58,15 @@ __device__ __forceinline__ float phi(float x) {
 
 __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLmax), kLmax); }
 
-// Check-node update (Eq. 5) of one check for the 64 words of a tile.
-//   Mt: v->c messages [nnz][64] (already clamped); Et: new c->v messages [nnz][64];
-//   Zt: hard-decision masks [n] (bit l = decision of lane l's word).
-//   E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from a
-//   prefix and a suffix (no total-minus-self), sign_j = parity of the other signs.
-// Returns the parity of the decisions over the check: the syndrome bit (Eq. 1) of
-// the decisions the incoming messages were computed with.
+// Check rule (Eq. 5) on one lane's incoming messages mv[0..dc) (already clamped):
+// E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from a
+// prefix and a suffix (no total-minus-self), sign_j = parity of the other signs.
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 template <int DC>
-__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et,
-                                            const unsigned long long *Zt, const int32_t *__restrict__ col_idx,
-                                            int e0, int dc, int lane, bool store) {
+__device__ __forceinline__ void check_core(const float *mv, int dc, float *eout) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
-  float mv[DMAX], ph[DMAX], pre[DMAX];
-  unsigned long long zx = 0;
-#pragma unroll
-  for (int j = 0; j < DMAX; ++j) {
-    if (FIXED || j < dc) {
-      mv[j] = Mt[(e0 + j) * TW + lane];
-      zx ^= Zt[col_idx[e0 + j]];
-    }
-  }
+  float ph[DMAX], pre[DMAX];
   uint32_t sg = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
@@ -103,11 +89,36 @@ __device__ __forceinline__ int check_update(const float *__restrict__ Mt, float 
   for (int j = DMAX - 1; j >= 0; --j) {
     if (FIXED || j < dc) {
       const float mag = phi(pre[j] + suf);
-      const float e = (((sg >> j) ^ tot) & 1u) ? -mag : mag;
-      if (store) Et[(e0 + j) * TW + lane] = e;
+      eout[j] = (((sg >> j) ^ tot) & 1u) ? -mag : mag;
       suf += ph[j];
     }
   }
+}
+
+// Check-node update of one check for the 64 words of a tile.
+//   Mt: v->c messages [nnz][64] (clamped); Et: new c->v messages [nnz][64];
+//   Zt: hard-decision masks [n] (bit l = decision of lane l's word).
+// Returns the parity of the decisions over the check: the syndrome bit (Eq. 1) of
+// the decisions the incoming messages were computed with.
+template <int DC>
+__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et,
+                                            const unsigned long long *Zt, const int32_t *__restrict__ col_idx,
+                                            int e0, int dc, int lane, bool store) {
+  constexpr int DMAX = DC > 0 ? DC : -DC;
+  constexpr bool FIXED = DC > 0;
+  float mv[DMAX], ev[DMAX];
+  unsigned long long zx = 0;
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) {
+    if (FIXED || j < dc) {
+      mv[j] = Mt[(e0 + j) * TW + lane];
+      zx ^= Zt[col_idx[e0 + j]];
+    }
+  }
+  check_core<DC>(mv, dc, ev);
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j)
+    if ((FIXED || j < dc) && store) Et[(e0 + j) * TW + lane] = ev[j];
   return (int)((zx >> lane) & 1ull);
 }
 

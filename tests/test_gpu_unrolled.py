@@ -1,0 +1,124 @@
+"""Differentiable form: unrolled weighted forward and hand-written adjoint vs the FP64 oracle,
+the torch FP64 reference gradient and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2201_04265_amd as P
+
+    assert torch.cuda.is_available()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c5(P):
+    code = W.code("c5")
+    g = P.Graph.from_code(code)
+    w = W.c5_weights(10)
+    return code, g, w
+
+
+def bce(post, cw):
+    sp = torch.nn.functional.softplus
+    return (cw * sp(post) + (1.0 - cw) * sp(-post)).mean()
+
+
+def gpu_grads(P, g, llr, w, cw):
+    x = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda().requires_grad_(True)
+    wt = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).cuda().requires_grad_(True)
+    post = P.unrolled_decode(g, x, wt)
+    loss = bce(post, torch.from_numpy(cw.astype(np.float32)).cuda())
+    loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), post.detach().cpu().numpy(), x.grad.cpu().numpy(), wt.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,cfg,T", [("c5", 5, 10), ("c1", 1, 7), ("c3", 3, 4)])
+def test_all_ones_weights_equal_plain_bitwise(P, name, cfg, T):
+    code = W.code(name)
+    g = P.Graph.from_code(code)
+    wd = W.words(name, cfg, 0, 2.0, 0, 300, fp32=True)
+    x = torch.from_numpy(wd.llr).cuda()
+    w = torch.ones((T, code.nnz), dtype=torch.float32, device="cuda")
+    post_u = P.unrolled_decode(g, x, w)
+    _, post_p, iters = P.decode(g, x, T, early_stop=False)
+    torch.cuda.synchronize()
+    assert torch.all(iters == T)
+    assert torch.equal(post_u, post_p)
+
+
+def test_forward_matches_oracle(P, c5, oracle_lib):
+    code, g, w = c5
+    wd = W.words("c5", 5, 0, 2.0, 0, 200, fp32=True)
+    post = P.unrolled_decode(g, torch.from_numpy(wd.llr).cuda(), torch.from_numpy(w).cuda()).cpu().numpy()
+    ref = oracle_lib.unrolled(code, wd.llr, w.astype(np.float64))
+    rel = np.abs(post - ref) / np.maximum(np.abs(ref), 1.0)
+    print("max rel", rel.max())
+    assert rel.max() <= 1e-4
+
+
+def test_adjoint_matches_reference_gradient(P, c5):
+    from oracle import grad
+
+    code, g, w = c5
+    wd = W.words("c5", 5, 0, 2.0, 0, 32, fp32=True)
+    loss_g, _, gl, gw = gpu_grads(P, g, wd.llr, w, wd.cw)
+    loss_r, rl, rw = grad.reference_grad(code, wd.llr.astype(np.float64), w.astype(np.float64), wd.cw)
+    assert loss_g == pytest.approx(loss_r, rel=1e-5)
+    for a, r in ((gw, rw), (gl, rl)):
+        err = np.linalg.norm(a - r) / np.linalg.norm(r)
+        per = np.abs(a - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
+        print("norm rel", err, "per-coord max", per.max())
+        assert err <= 1e-3
+        assert per.max() <= 1e-2
+
+
+def test_adjoint_matches_finite_differences(P, c5):
+    """Central differences of the FP64 C forward on 16 words at sampled weights and LLRs."""
+    from oracle import grad
+
+    code, g, w = c5
+    wd = W.words("c5", 5, 0, 2.0, 0, 16, fp32=True)
+    _, _, gl, gw = gpu_grads(P, g, wd.llr, w, wd.cw)
+    rng = np.random.default_rng(7)
+    # sample weights on edges of the first iterations and of the last one, LLRs of any word
+    cw_ = [(int(rng.integers(10)), int(rng.integers(code.nnz))) for _ in range(24)]
+    cl_ = [(int(rng.integers(16)), int(rng.integers(code.n))) for _ in range(24)]
+    fw, fl = grad.fd_grad(code, wd.llr.astype(np.float64), w.astype(np.float64), wd.cw, cw_, cl_)
+    aw = np.array([gw[t, e] for t, e in cw_])
+    al = np.array([gl[b, v] for b, v in cl_])
+    for a, f in ((aw, fw), (al, fl)):
+        err = np.linalg.norm(a - f) / np.linalg.norm(f)
+        per = np.abs(a - f) / np.maximum(np.abs(f), 1e-3 * np.abs(f).max())
+        print("FD norm rel", err, "per-coord", per.max())
+        assert err <= 1e-3
+        assert per.max() <= 1e-2
+
+
+def test_full_size_deterministic(P, c5):
+    """Full batch (4096 words, 10 iterations): finite gradients, bitwise repeatable."""
+    code, g, w = c5
+    wd = W.words("c5", 5, 0, 2.0, 0, 4096, fp32=True)
+    a = gpu_grads(P, g, wd.llr, w, wd.cw)
+    b = gpu_grads(P, g, wd.llr, w, wd.cw)
+    assert np.isfinite(a[3]).all() and np.isfinite(a[2]).all()
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y)
+
+
+def test_zero_iterations(P, c5):
+    code, g, _ = c5
+    wd = W.words("c5", 5, 0, 2.0, 0, 70, fp32=True)
+    x = torch.from_numpy(wd.llr).cuda().requires_grad_(True)
+    w = torch.zeros((0, code.nnz), dtype=torch.float32, device="cuda", requires_grad=True)
+    post = P.unrolled_decode(g, x, w)
+    assert torch.equal(post.detach(), x.detach())
+    post.sum().backward()
+    assert torch.equal(x.grad, torch.ones_like(x))
