@@ -129,9 +129,106 @@ def summarize(torch, name, ms, outs, cw, ebn0s, B, code, extra):
     return d
 
 
+def bench_c4(args, torch, P):
+    """Mixed batch: 4096 words round-robin over six codes at their own Eb/N0, max 50 iterations.
+    Per-code plain launches (back to back on one stream) vs one batched persistent launch."""
+    from synth import workloads as W
+
+    names = W.C4_CODES
+    counts = W.c4_counts(W.C4["batch"])
+    ebn0 = W.c4_ebn0()
+    codes = [W.code(nm) for nm in names]
+    graphs = [P.Graph.from_code(c) for c in codes]
+    words = [W.words(nm, 4, 0, float(ebn0[i]), 0, counts[i], fp32=True, code_key=i) for i, nm in enumerate(names)]
+    llrs = [torch.from_numpy(w.llr).cuda() for w in words]
+    cws = [torch.from_numpy(w.cw).cuda() for w in words]
+    stream = torch.cuda.current_stream()
+    wss = [torch.empty(P.workspace_size(g, x.shape[0]), dtype=torch.uint8, device="cuda") for g, x in zip(graphs, llrs)]
+    pouts = [(torch.empty(x.shape, dtype=torch.uint8, device="cuda"), torch.empty(x.shape, device="cuda"),
+              torch.empty((x.shape[0],), dtype=torch.int32, device="cuda")) for x in llrs]
+
+    def plain():
+        for g, x, ws, o in zip(graphs, llrs, wss, pouts):
+            P.decode(g, x, MAX_ITERS, True, workspace=ws, out=o)
+
+    ms_plain = time_launches(torch, plain, args.steps, args.warmup, stream)
+    batch = P.Batch(graphs, llrs, MAX_ITERS)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True)
+    resolved, _ = batch.resolve(shape)
+    ws = batch.workspace(shape)
+    ms_batched = time_launches(torch, lambda: batch.run(True, shape, ws), args.steps, args.warmup, stream)
+    plan = P.Plan(batch, True, shape)
+    ms_plan = time_launches(torch, lambda: plan.launch(), args.steps, args.warmup, stream)
+    bits = sum(int(x.numel()) for x in llrs)
+    useful = sum(int(o[2].to(torch.int64).sum().item()) * c.nnz for o, c in zip(batch.outs, codes))
+    per_code = []
+    same = True
+    for i, c in enumerate(codes):
+        bo, po = batch.outs[i], pouts[i]
+        same &= all(bool(torch.equal(a, b)) for a, b in zip(bo, po))
+        per_code.append({"code": c.name, "n": c.n, "edges": c.nnz, "words": counts[i], "ebn0_db": float(ebn0[i]),
+                         "mean_iters": float(bo[2].float().mean().item()),
+                         "ber_coded": float((bo[0] != cws[i]).float().mean().item()),
+                         "ber_coded_plain": float((po[0] != cws[i]).float().mean().item())})
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
+    return {"metric": "coded Gbit/s, mixed six-code batch (4096 words); batched vs per-code plain launches",
+            "value": bits / (avg(ms_batched) * 1e-3) / 1e9, "unit": "coded Gbit/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": avg(ms_batched), "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "4096 words round-robin over six seeded codes, each at its own Eb/N0 in [1,4] dB, "
+                                   "max 50 iterations, early stop"},
+            "batched_ms": avg(ms_batched), "batched_plan_ms": avg(ms_plan), "per_code_plain_ms": avg(ms_plain),
+            "speedup_vs_per_code_plain": avg(ms_plain) / avg(ms_batched),
+            "edge_updates_per_s": useful / (avg(ms_batched) * 1e-3), "shape": resolved.as_dict(len(codes)),
+            "outputs_bitwise_equal": same, "per_code": per_code}
+
+
+def bench_c5(args, torch, P):
+    """Unrolled (3,6) n=1024 decoder, 10 weighted iterations, 4096 words at 2.0 dB: forward, and
+    forward + BCE loss + backward (gradients w.r.t. weights and channel LLRs)."""
+    from synth import workloads as W
+
+    code = W.code("c5")
+    g = P.Graph.from_code(code)
+    wd = W.words("c5", 5, 0, 2.0, 0, W.C5["batch"], fp32=True)
+    x = torch.from_numpy(wd.llr).cuda()
+    cw = torch.from_numpy(wd.cw.astype("float32")).cuda()
+    w = torch.from_numpy(W.c5_weights(W.C5["iters"])).cuda()
+    stream = torch.cuda.current_stream()
+    sp = torch.nn.functional.softplus
+
+    def fwd():
+        with torch.no_grad():
+            return P.unrolled_decode(g, x, w)
+
+    def fwd_bwd():
+        xr = x.detach().requires_grad_(True)
+        wr = w.detach().requires_grad_(True)
+        post = P.unrolled_decode(g, xr, wr)
+        loss = (cw * sp(post) + (1.0 - cw) * sp(-post)).mean()
+        loss.backward()
+        return loss
+
+    ms_f = time_launches(torch, fwd, args.steps, args.warmup, stream)
+    ms_fb = time_launches(torch, fwd_bwd, args.steps, args.warmup, stream)
+    T, B = W.C5["iters"], x.shape[0]
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
+    return {"metric": "unrolled differentiable decoder, (3,6) n=1024, T=10, 4096 words: forward and "
+                      "forward+backward", "value": B * code.n / (avg(ms_fb) * 1e-3) / 1e9,
+            "unit": "coded Gbit/s (forward+backward)", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": avg(ms_fb), "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "forward_ms": avg(ms_f), "forward_backward_ms": avg(ms_fb),
+            "forward_edge_updates_per_s": B * T * code.nnz / (avg(ms_f) * 1e-3),
+            "config": {"workload": "(3,6) n=1024 girth>=6, 4096 words at 2.0 dB, 10 unrolled iterations, per-edge "
+                                   "weights N(1, 0.1^2), mean BCE loss"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2: (3,6) n=4096 Eb/N0 sweep (default); c4: six-code mixed batch, batched vs per-code "
+                         "plain launches; c5: unrolled differentiable form, forward and forward+backward")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=65536, help="words per Eb/N0 point")
@@ -159,6 +256,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
+        return
+
+    if args.workload == "c4":
+        print(json.dumps(bench_c4(args, torch, P)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_c5(args, torch, P)), flush=True)
         return
 
     code, ebn0s, llr, cw = make_inputs(args, torch)

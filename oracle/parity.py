@@ -1,4 +1,6 @@
-"""Parity rule between the FP32 GPU decoder and the FP64 oracle.
+"""ORACLE -- test infrastructure only.
+
+Parity rule between the FP32 GPU decoder and the FP64 oracle.
 
 Per word:
   * hard decisions and iterations used are identical (P-hard).  A word whose

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity import assert_parity, compare
+from oracle.parity import assert_parity, compare
 from synth import workloads as W
 
 pytestmark = pytest.mark.gpu

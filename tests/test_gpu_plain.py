@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity import assert_parity, compare
+from oracle.parity import assert_parity, compare
 from synth import codes, gf2, workloads
 
 pytestmark = pytest.mark.gpu

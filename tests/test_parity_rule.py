@@ -1,7 +1,7 @@
 """The parity checker itself, exercised on the CPU with mistakes planted in oracle outputs."""
 import numpy as np
 
-from parity import assert_parity, compare
+from oracle.parity import assert_parity, compare
 from synth import workloads
 
 
