@@ -31,8 +31,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batched"
+
+# HBM bytes per launch of the batched kernel on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs scaled by a 1 GiB copy (profiles/decode_c2_sweep.md); valid only for the kernel sources they
+# were measured with (sha1 over KERNEL_SOURCES), reported as null otherwise.
+KERNEL_SOURCES = ["paper_2201_04265_amd/csrc/spa_core.h", "paper_2201_04265_amd/csrc/tile.h",
+                  "paper_2201_04265_amd/csrc/multi.hip", "paper_2201_04265_amd/csrc/internal.h"]
+COUNTER_TRAFFIC = {"sources_sha1": "af8949c8bf987d13f8e379c19e1d71d14e46e5d3", "bytes_per_launch": 1676686595905,
+                   "read_bytes": 912527264929, "write_bytes": 764159330976}
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
+
+
+def counter_traffic():
+    import hashlib
+
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return COUNTER_TRAFFIC["bytes_per_launch"] if h.hexdigest() == COUNTER_TRAFFIC["sources_sha1"] else None
 
 
 def log(msg):
@@ -325,7 +343,9 @@ def main():
         "edge_updates_per_s": head["edge_updates_per_s"],
         "forms": results,
         "roofline": {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["achieved_gb_s"] / HBM_PEAK_GBS, "traffic": None, "kernel": head["kernel"],
+                     "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if head["form"] == "batched" and B == 65536 else None,
+                     "kernel": head["kernel"],
                      "avg_launch_ms": head["ms_per_step"], "alg_bytes_per_launch": head["alg_bytes_per_launch"],
                      "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
                      "unit_of_work": "useful word-iteration (sum of iterations used over words) plus LLR "

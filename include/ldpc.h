@@ -123,7 +123,8 @@ typedef struct {
   int32_t *iters_used;/* [batch] out */
 } ldpc_job;
 
-/* Launch shape of a batched decode: waves per workgroup (0 = 8); 64-word slots
+/* Launch shape of a batched decode: waves per workgroup (0 = 16 when the batch has
+ * fewer 64-word tiles than the GPU has compute units, else 8); 64-word slots
  * (workgroups) per code (0 = automatic: the resident capacity of the GPU shared
  * in proportion to words x edges, at most one slot per 64 words); refill: a slot
  * writes out and replaces its stopped words once this many of its 64 lanes wait

@@ -204,7 +204,15 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     return set_error(LDPC_ERR_INVALID_ARG, "need 1.." + std::to_string(LDPC_MAX_CODES) + " codes");
   ldpc_multi_shape sh{};
   if (shape_in) sh = *shape_in;
-  if (sh.waves == 0) sh.waves = 8;
+  if (sh.waves == 0) {
+    // small batches (fewer 64-word tiles than compute units) get the widest workgroups
+    int dev = 0, cus = 0;
+    LDPC_HIP_CHECK(hipGetDevice(&dev));
+    LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    long tiles = 0;
+    for (int q = 0; q < ncodes; ++q) tiles += (jobs[q].batch + TW - 1) / TW;
+    sh.waves = tiles < cus ? 16 : 8;
+  }
   if (sh.waves < 1 || sh.waves > 16) return set_error(LDPC_ERR_INVALID_ARG, "waves must be in 1..16");
   if (sh.refill == 0) sh.refill = 1;
   if (sh.refill < 1 || sh.refill > kTile) return set_error(LDPC_ERR_INVALID_ARG, "refill must be in 1..64");
