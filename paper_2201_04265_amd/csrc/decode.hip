@@ -24,7 +24,7 @@
 namespace ldpc {
 
 template <int DC, int DV>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
     plain_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                         int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard, float *__restrict__ post,
                         int32_t *__restrict__ iters) {

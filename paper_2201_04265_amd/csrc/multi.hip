@@ -22,7 +22,9 @@
 namespace ldpc {
 
 // Channel LLRs of fresh words into R (the variable phase then derives their first
-// messages and decisions with all incoming messages taken as 0).
+// messages and decisions with all incoming messages taken as 0).  A stopped word's
+// outputs are recomputed from its last messages, which nothing overwrites while it
+// waits: its lane's check-phase stores are masked off from the step it stops.
 __device__ __forceinline__ void ingest_lanes(const GraphDev &g, const float *__restrict__ llr, TileState st, int word,
                                              bool fresh, int wave, int W, int lane) {
   if (!fresh) return;
@@ -30,18 +32,31 @@ __device__ __forceinline__ void ingest_lanes(const GraphDev &g, const float *__r
   for (int v = wave; v < g.n; v += W) st.R[v * TW + lane] = src[v];
 }
 
-// Outputs of the lanes in `out`: their last posterior (kept in L by the variable
-// phase) and its decisions, straight into the word's row of [B][n].
-__device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, int word, bool out,
-                                             float *__restrict__ post, uint8_t *__restrict__ hard, int wave, int W,
-                                             int lane) {
+// Outputs of the lanes in `out`: the posterior of their last iteration, recomputed
+// from their last messages (in E1 when `odd`, else E0; R itself when they stopped
+// before any iteration) with the variable phase's summation order, and its
+// decisions, straight into the word's row of [B][n].
+template <int DV>
+__device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, int word, bool out, bool odd,
+                                             int it_lane, float *__restrict__ post, uint8_t *__restrict__ hard,
+                                             int wave, int W, int lane) {
+  constexpr int DMAX = DV > 0 ? DV : -DV;
   if (!out) return;
+  const float *Ep = odd ? st.E1 : st.E0;
   float *prow = post + (size_t)word * (size_t)g.n;
   uint8_t *hrow = hard + (size_t)word * (size_t)g.n;
   for (int v = wave; v < g.n; v += W) {
-    const float x = st.L[v * TW + lane];
-    prow[v] = x;
-    hrow[v] = x <= 0.0f ? 1 : 0;
+    int p0, dv;
+    var_range<DV>(g, v, p0, dv);
+    float L = st.R[v * TW + lane];
+    if (it_lane > 0) {
+      // same terms in the same order as var_posterior: R + E_0 + E_1 + ...
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j)
+        if (DV > 0 || j < dv) L += Ep[g.var_edges[p0 + j] * TW + lane];
+    }
+    prow[v] = L;
+    hrow[v] = L <= 0.0f ? 1 : 0;
   }
 }
 
@@ -56,7 +71,7 @@ __device__ __forceinline__ void slot_var_phase(const GraphDev &g, TileState st, 
   for (int v = wave; v < g.n; v += W) {
     int p0, dv;
     var_range<DV>(g, v, p0, dv);
-    var_update<DV, true>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running || fresh, fresh, st.L);
+    var_update<DV, true>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running || fresh, fresh);
   }
 }
 
@@ -67,7 +82,7 @@ template <int DC, int DV>
 __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop, int refill_min,
                          unsigned long long *unsat_w, int *lane_word, int wave, int W, int lane) {
   const GraphDev &g = J.g;
-  const TileState st = tile_state_block(J.ws + (size_t)local_slot * slot_bytes(g.nnz, g.n), g.nnz, g.n);
+  const TileState st = tile_state_block(J.ws + (size_t)local_slot * tile_bytes(g.nnz, g.n), g.nnz, g.n);
 
   if (wave == 0) {
     int base = 0;
@@ -79,6 +94,7 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
   int word = lane_word[lane];
   bool has = word >= 0;  // lane holds a word (running or pending)
   bool pending = false;  // its word has stopped and waits for output
+  bool odd = false;      // its last messages are in E1 (else E0)
   int it_lane = 0;
   if (__ballot(has) == 0ull) return;  // uniform: nothing left for this slot
   ingest_lanes(g, J.llr, st, word, has, wave, W, lane);
@@ -101,13 +117,14 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
     for (int w = 0; w < W; ++w) um |= unsat_w[w];
     const bool lane_unsat = (um >> lane) & 1ull;
     const bool stop = active && ((early_stop && !lane_unsat) || it_lane == J.max_iters);
+    if (stop) odd = (G & 1) != 0;  // E^(it) was written at step G-1 into E[G & 1]
     pending = pending || stop;
     const bool running = active && !stop;
     const unsigned long long pmask = __ballot(pending);
     const unsigned long long rmask = __ballot(running);
     bool fresh = false;
     if (pmask != 0ull && (__popcll(pmask) >= refill_min || rmask == 0ull)) {  // same in every wave
-      egress_lanes(g, st, word, pending, J.post, J.hard, wave, W, lane);
+      egress_lanes<DV>(g, st, word, pending, odd, it_lane, J.post, J.hard, wave, W, lane);
       if (wave == 0) {
         if (pending) J.iters[word] = it_lane;
         int base = 0;
@@ -250,7 +267,7 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
   size_t bytes = 256;  // counters
   for (int q = 0; q < ncodes; ++q) {
     if (jobs[q].batch == 0) sh.slots[q] = 0;
-    bytes += (size_t)sh.slots[q] * slot_bytes(graphs[q]->nnz, graphs[q]->n);
+    bytes += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
   }
   if (shape_out) *shape_out = sh;
   if (ws_bytes) *ws_bytes = bytes;
@@ -283,7 +300,7 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
     J.dc_max = graphs[q]->dc_max;
     J.ws = p;
     J.order = orders ? orders[q] : nullptr;
-    p += (size_t)sh.slots[q] * slot_bytes(graphs[q]->nnz, graphs[q]->n);
+    p += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
     slot += sh.slots[q];
   }
   *grid = slot;

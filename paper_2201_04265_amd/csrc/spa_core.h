@@ -152,13 +152,12 @@ __device__ __forceinline__ float var_posterior(float r, const float *__restrict_
 // Variable-node update: posterior L (Eq. 7) -> decision mask Zt[v] (Eq. 8, z = [L <= 0]),
 // and the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6) as prefix + suffix.
 // With ZERO_E, lanes with `fresh` set see all incoming messages as 0 (a word that has
-// not been through a check phase yet): M = clamp(R), z = [R <= 0].  With Lt, the
-// posterior of the storing lanes is also written to Lt[v] (R itself for fresh lanes).
+// not been through a check phase yet): M = clamp(R), z = [R <= 0].
 template <int DV, bool ZERO_E = false>
 __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const float *__restrict__ Et,
                                            float *__restrict__ Mt, unsigned long long *Zt,
                                            const int32_t *__restrict__ var_edges, int p0, int dv, int v, int lane,
-                                           bool store, bool fresh = false, float *__restrict__ Lt = nullptr) {
+                                           bool store, bool fresh = false) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
   constexpr bool FIXED = DV > 0;
   float ev[DMAX], pre[DMAX];
@@ -175,7 +174,6 @@ __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const f
   }
   const unsigned long long z = __ballot(L <= 0.0f);
   if (lane == 0) Zt[v] = z;
-  if (Lt != nullptr && store) Lt[v * TW + lane] = L;
   float suf = 0.0f;
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {

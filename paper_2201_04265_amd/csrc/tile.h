@@ -13,7 +13,6 @@ namespace ldpc {
 struct TileState {
   float *E0, *E1, *M, *R;
   unsigned long long *Z;
-  float *L;  // posterior [n][64]; batched form only
 };
 
 // Bytes of one tile's state, each array 256-byte aligned.
@@ -24,12 +23,7 @@ __host__ __device__ inline size_t tile_bytes(int64_t nnz, int32_t n) {
   return 3 * e + v + z;
 }
 
-// Bytes of one slot of the batched form: a tile plus the posterior L [n][64].
-__host__ __device__ inline size_t slot_bytes(int64_t nnz, int32_t n) {
-  return tile_bytes(nnz, n) + (((size_t)n * TW * sizeof(float) + 255) & ~size_t(255));
-}
-
-// Tile state carved from one contiguous per-tile block (L follows Z when present).
+// Tile state carved from one contiguous per-tile block.
 __device__ __forceinline__ TileState tile_state_block(char *base, int64_t nnz, int32_t n) {
   const size_t e = ((size_t)nnz * TW * sizeof(float) + 255) & ~size_t(255);
   const size_t v = ((size_t)n * TW * sizeof(float) + 255) & ~size_t(255);
@@ -39,7 +33,6 @@ __device__ __forceinline__ TileState tile_state_block(char *base, int64_t nnz, i
   s.M = (float *)(base + 2 * e);
   s.R = (float *)(base + 3 * e);
   s.Z = (unsigned long long *)(base + 3 * e + v);
-  s.L = (float *)(base + tile_bytes(nnz, n));
   return s;
 }
 
