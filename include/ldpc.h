@@ -108,6 +108,24 @@ ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, i
                                uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
                                void *workspace, size_t ws_bytes, int32_t waves, hipStream_t stream);
 
+/* ---- stream form: one word per workgroup, state in LDS -------------------- */
+
+/* LDS bytes one word's decoding state needs (9 x edges + 8 x n) and whether it fits
+ * one workgroup of the current device (*supported = 1). */
+ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported);
+
+/*
+ * Same contract and bit-identical outputs as ldpc_decode, computed by the stream
+ * form (Sec. III-B's spreading of one word over many workers, here the threads of
+ * one workgroup with every message in LDS).  Persistent workgroups take words from
+ * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024; 0 = by
+ * code size).  workspace: >= 256 device bytes (the counter).  Returns
+ * LDPC_ERR_UNSUPPORTED when the word state exceeds the LDS of one workgroup.
+ */
+ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
+                               uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
+                               void *workspace, size_t ws_bytes, int32_t threads, hipStream_t stream);
+
 /* ---- batched persistent form --------------------------------------------- */
 
 /* Most codes one batched launch serves. */

@@ -52,3 +52,35 @@ def decode(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = T
                                   int(waves), s)
     check("ldpc_decode", st)
     return hard, post, iters
+
+
+def stream_supported(graph: Graph) -> bool:
+    nb, ok = ctypes.c_size_t(), ctypes.c_int32()
+    check("ldpc_stream_lds_bytes", lib().ldpc_stream_lds_bytes(graph.handle, ctypes.byref(nb), ctypes.byref(ok)))
+    return bool(ok.value)
+
+
+def decode_stream(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = True, threads: int = 0,
+                  workspace: torch.Tensor | None = None, out=None, stream=None):
+    """Stream form (one word per workgroup, state in LDS); same outputs as decode()."""
+    if not llr.is_cuda or llr.dim() != 2 or llr.shape[1] != graph.n:
+        raise ValueError("llr must be a cuda tensor of shape [B, n]")
+    if llr.dtype not in (torch.float32, torch.float64):
+        raise ValueError("llr must be float32 or float64")
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        hard = torch.empty((B, graph.n), dtype=torch.uint8, device=dev)
+        post = torch.empty((B, graph.n), dtype=torch.float32, device=dev)
+        iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    else:
+        hard, post, iters = out
+    if workspace is None:
+        workspace = torch.empty((256,), dtype=torch.uint8, device=dev)
+    flags = LLR_F64 if llr.dtype == torch.float64 else 0
+    check("ldpc_decode_stream",
+          lib().ldpc_decode_stream(graph.handle, _ptr(llr), B, int(max_iters), int(bool(early_stop)), flags,
+                                   _ptr(hard), _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(),
+                                   int(threads), ctypes.c_void_p(stream_handle(stream))))
+    return hard, post, iters

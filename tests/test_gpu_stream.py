@@ -1,0 +1,110 @@
+"""Stream form (one word per workgroup, state in LDS): bit-identical to the plain decoder,
+parity with the FP64 oracle, and the LDS limit reported as unsupported."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.parity import assert_parity, compare
+from synth import codes, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2201_04265_amd as P
+
+    assert torch.cuda.is_available()
+    return P
+
+
+def both(P, g, llr, T, es=True, threads=0):
+    x = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    a = P.decode(g, x, T, es)
+    b = P.decode_stream(g, x, T, es, threads=threads)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in a], [t.cpu().numpy() for t in b]
+
+
+def same(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_c1_equals_plain_and_oracle(P, oracle_lib):
+    code = W.code("c1")
+    g = P.Graph.from_code(code)
+    wd = W.words("c1", 1, 0, 2.0, 0, 1000, fp32=False)
+    a, b = both(P, g, wd.llr, 20)
+    same(a, b)
+    oh, op, oi, _ = oracle_lib.decode(code, wd.llr, 20, True)
+    assert_parity(compare(oh, op, oi, *b, oracle_lib, code, wd.llr, 20))
+
+
+@pytest.mark.parametrize("ebn0,key", [(1.0, 0), (2.0, 2)])
+def test_c2_equals_plain(P, ebn0, key):
+    code = W.code("c2")
+    g = P.Graph.from_code(code)
+    assert P.stream_supported(g)
+    wd = W.words("c2", 2, key, ebn0, 0, 3000, fp32=True)
+    a, b = both(P, g, wd.llr, 50)
+    same(a, b)
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_workgroup_sizes_agree(P, threads):
+    code = W.code("c5")
+    g = P.Graph.from_code(code)
+    wd = W.words("c5", 5, 0, 1.5, 0, 777, fp32=True)
+    a, b = both(P, g, wd.llr, 30, True, threads)
+    same(a, b)
+
+
+def test_fixed_and_zero_iterations(P):
+    code = W.code("c5")
+    g = P.Graph.from_code(code)
+    wd = W.words("c5", 5, 0, 2.0, 0, 300, fp32=True)
+    for T, es in ((9, False), (0, False), (0, True)):
+        a, b = both(P, g, wd.llr, T, es)
+        same(a, b)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_irregular_codes(P, oracle_lib, seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(60, 400))
+    m = int(rng.integers(n // 4, n // 2))
+    chk, var = [], []
+    for c in range(m):
+        d = int(rng.integers(2, 25))
+        vs = rng.choice(n, size=min(d, n), replace=False)
+        chk += [c] * len(vs)
+        var += list(vs)
+    code = codes.from_edges(m, n, np.array(chk), np.array(var))
+    g = P.Graph.from_code(code)
+    llr = rng.normal(2.0, 2.0, size=(int(rng.integers(1, 300)), n)).astype(np.float32)
+    a, b = both(P, g, llr, 15)
+    same(a, b)
+
+
+def test_mixed_batch_codes(P):
+    """Every mixed-batch code that fits the LDS of a workgroup decodes identically in both forms."""
+    for i, name in enumerate(W.C4_CODES):
+        code = W.code(name)
+        g = P.Graph.from_code(code)
+        if not P.stream_supported(g):
+            assert code.n >= 5000  # n=16384 and the Z=128 quasi-cyclic code need more than 160 KB
+            continue
+        wd = W.words(name, 4, 0, float(W.c4_ebn0()[i]), 0, 200, fp32=True, code_key=i)
+        a, b = both(P, g, wd.llr, 50)
+        same(a, b)
+
+
+def test_too_large_is_unsupported(P):
+    code = W.code("c3")
+    g = P.Graph.from_code(code)
+    assert not P.stream_supported(g)
+    x = torch.zeros((4, code.n), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.LdpcError) as e:
+        P.decode_stream(g, x, 10)
+    assert e.value.status == -5
