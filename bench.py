@@ -6,16 +6,20 @@ information bits, systematic encoding, BPSK/AWGN, FP32 LLRs), at most 50
 iterations with per-word syndrome early stop.  The five points form one batch of
 327680 words, resident in HBM before timing starts.
 
-Two forms decode the same batch:
-  plain    one ldpc_decode launch (64-word tiles, each runs until its slowest word)
+Three forms decode the same batch, with bitwise-identical outputs:
+  plain    one ldpc_decode launch (64-word tiles in HBM, each runs until its slowest word)
   batched  one ldpc_decode_multi persistent launch with per-word refill, launch
            shape from the autotuner (cached per code / batch / architecture)
-`value` is the batched form's coded Gbit/s; both forms are reported.
+  stream   one ldpc_decode_stream launch: one word per workgroup, its whole state in
+           LDS, persistent workgroups taking words from a counter
+`value` is the stream form's coded Gbit/s (the fastest); every form is reported.
 
 Also reported: edge updates/s (useful iterations only), per-point iterations /
-BER / FER, the roofline of the batched kernel (algorithmic HBM bytes of the
-useful iterations / average launch duration from HIP events on the launch
-stream), and the FP64 CPU oracle timed on a bounded sample of the same words.
+BER / FER, the roofline of the headline kernel -- the stream kernel is bound by
+VALU issue, so its figure is VALU issue slots per useful edge-iteration (counted
+in the compiled code) over the launch time against 256 CU x 64 lanes x 2.4 GHz;
+the HBM forms carry their byte rooflines -- and the FP64 CPU oracle timed on a
+bounded sample of the same words.
 """
 from __future__ import annotations
 
@@ -41,6 +45,11 @@ COUNTER_TRAFFIC = {"sources_sha1": "af8949c8bf987d13f8e379c19e1d71d14e46e5d3", "
                    "read_bytes": 912527264929, "write_bytes": 764159330976}
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
+# VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
+# code: 316 VALU instructions per degree-6 check (36 of them quarter-rate transcendentals)
+# and 30 per degree-3 variable; a quarter-rate instruction occupies 4 issue slots.
+STREAM_VALU_SLOTS_PER_EDGE = (316 + 3 * 36) / 6.0 + 30 / 3.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-operations per second, 1 slot each
 
 
 def counter_traffic():
@@ -51,6 +60,24 @@ def counter_traffic():
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return COUNTER_TRAFFIC["bytes_per_launch"] if h.hexdigest() == COUNTER_TRAFFIC["sources_sha1"] else None
+
+
+def roofline(head, code, B):
+    if head["form"] == "stream":
+        a = head["achieved_valu_tops"]
+        return {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": a / VALU_PEAK_TOPS,
+                "traffic": None, "kernel": head["kernel"], "avg_launch_ms": head["ms_per_step"],
+                "unit_of_work": "useful edge-iteration x VALU issue slots per edge-iteration (%.2f, compiled "
+                                "code; quarter-rate transcendentals count 4)" % STREAM_VALU_SLOTS_PER_EDGE,
+                "hbm_alg_gb_s_equivalent": head["achieved_gb_s"]}
+    return {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
+            "traffic": counter_traffic() if head["form"] == "batched" and B == 65536 else None,
+            "kernel": head["kernel"], "avg_launch_ms": head["ms_per_step"],
+            "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+            "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
+            "unit_of_work": "useful word-iteration (sum of iterations used over words) plus LLR in / posterior "
+                            "and decisions out per word"}
 
 
 def log(msg):
@@ -250,7 +277,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=65536, help="words per Eb/N0 point")
-    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--forms", default="plain,batched,stream")
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the library's default shape")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -322,7 +349,23 @@ def main():
             results["batched"]["bitwise_equal_to_plain"] = all(
                 bool(torch.equal(a, b)) for a, b in zip(batch.outs[0], plain_outs))
 
-    head = results.get("batched") or results["plain"]
+    if "stream" in forms:
+        outs = (torch.empty(llr.shape, dtype=torch.uint8, device="cuda"),
+                torch.empty(llr.shape, dtype=torch.float32, device="cuda"),
+                torch.empty((llr.shape[0],), dtype=torch.int32, device="cuda"))
+        ws = torch.empty((256,), dtype=torch.uint8, device="cuda")
+        ms = time_launches(torch, lambda: P.decode_stream(g, llr, MAX_ITERS, True, workspace=ws, out=outs),
+                           args.steps, args.warmup, stream)
+        results["stream"] = summarize(torch, "stream", ms, outs, cw, ebn0s, B, code,
+                                      {"kernel": "stream_decode_kernel<6,3>", "threads": 1024})
+        r = results["stream"]
+        r["valu_slots_per_edge_iteration"] = STREAM_VALU_SLOTS_PER_EDGE
+        r["achieved_valu_tops"] = r["edge_updates_per_s"] * STREAM_VALU_SLOTS_PER_EDGE / 1e12
+        if "plain" in results:
+            r["bitwise_equal_to_plain"] = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain_outs))
+        log(f"[bench] stream: {r['ms_per_step']:.1f} ms/step")
+
+    head = results.get("stream") or results.get("batched") or results["plain"]
     result = {
         "metric": METRIC,
         "value": head["coded_gbit_s"],
@@ -342,14 +385,7 @@ def main():
                    "form": head["form"], "words_per_step": int(llr.shape[0]), "edges": code.nnz},
         "edge_updates_per_s": head["edge_updates_per_s"],
         "forms": results,
-        "roofline": {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
-                     "traffic": counter_traffic() if head["form"] == "batched" and B == 65536 else None,
-                     "kernel": head["kernel"],
-                     "avg_launch_ms": head["ms_per_step"], "alg_bytes_per_launch": head["alg_bytes_per_launch"],
-                     "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
-                     "unit_of_work": "useful word-iteration (sum of iterations used over words) plus LLR "
-                                     "in / posterior and decisions out per word"},
+        "roofline": roofline(head, code, B),
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

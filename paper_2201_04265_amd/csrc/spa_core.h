@@ -22,57 +22,74 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // of the tanh rule, 2 atanh(prod tanh(a_i / 2)) = phi(sum phi(a_i)).  phi(0) = +inf
 // and phi(+inf) = 0, so a zero input message zeroes the others.
 // Evaluated from the hardware exp2 / log2 / reciprocal with two branch-free paths
-// (relative error a few 1e-7 over [0, inf)):
-//   x >= 1.386 (q = e^-x <= 1/4): the odd series 2 atanh(q) = 2q (1 + q^2/3 + ... + q^10/11),
-//                                 truncation < 5e-9;
-//   x <  1.386: phi = log((2 - d) / d) with d = 1 - e^-x, where d comes from the Taylor
-//               series of 1 - e^-x for x < 0.3 (no cancellation) and from 1 - q above.
-// e^-x is 2^-(x log2 e) with the product split in two parts, so q keeps ~1 ulp for x <= 20.
-__device__ __forceinline__ float phi(float x) {
-  constexpr float kL2eHi = 1.44269502162933349609375f;  // log2(e) rounded to float
-  constexpr float kL2eLo = 1.925963033500011079e-08f;   // log2(e) - kL2eHi
-  constexpr float kLn2 = 0.693147180559945309f;
-  x = fminf(x, 100.0f);  // phi(100) < 1e-43: the result is 0 either way, the split stays finite
-  const float y = x * kL2eHi;
-  const float ey = fmaf(x, kL2eHi, -y) + x * kL2eLo;
-  float q = __builtin_amdgcn_exp2f(-y);
-  q = fmaf(-q, ey * kLn2, q);  // 2^-(y + ey) ~ 2^-y (1 - ey ln 2)
+// (relative error below 1e-6 over [0, inf), below 4e-7 for x < 10):
+//   x >= 2 (q = e^-x <= 0.136): the odd series 2 atanh(q) = 2q (1 + q^2/3 + q^4/5 + q^6/7),
+//                               truncation < 2e-9;
+//   x <  2: phi = log((2 - d) / d) with d = 1 - e^-x, where d comes from the Taylor
+//           series x (1 - x/2 + x^2/6 - x^3/24 + x^4/120) for x < 0.15 (no cancellation)
+//           and from 1 - q above.
+// The check rule applies phi twice with a sum in between, so the inner sum is kept
+// in base-2 units (phi / ln 2): phi_to2 takes x and returns phi(x) / ln 2, phi_from2
+// takes y = x / ln 2 and returns phi(x).  e^-x = 2^(-x log2 e); the rounding of that
+// product only affects phi(x) for large x, where phi is tiny and only enters sums.
+constexpr float kL2e = 1.44269504088896341f;  // log2(e) = 1 / ln 2
+constexpr float kLn2 = 0.693147180559945309f;
+
+__device__ __forceinline__ float phi_core(float x, float q, float c) {
+  // x: argument, q = e^-x; returns c * phi(x) on the series path and the base-2
+  // logarithm of (2 - d) / d on the other (the caller scales it)
   const float s = q * q;
-  float p = fmaf(s, 1.0f / 11.0f, 1.0f / 9.0f);
-  p = fmaf(s, p, 1.0f / 7.0f);
-  p = fmaf(s, p, 1.0f / 5.0f);
-  p = fmaf(s, p, 1.0f / 3.0f);
-  p = fmaf(s, p, 1.0f);
-  const float big = 2.0f * q * p;
-  float t = fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f);
-  t = fmaf(x, t, 1.0f / 120.0f);
-  t = fmaf(x, t, -1.0f / 24.0f);
+  float p = fmaf(s, c / 7.0f, c / 5.0f);
+  p = fmaf(s, p, c / 3.0f);
+  p = fmaf(s, p, c);
+  const float big = q * p;
+  float t = fmaf(x, 1.0f / 120.0f, -1.0f / 24.0f);
   t = fmaf(x, t, 1.0f / 6.0f);
   t = fmaf(x, t, -0.5f);
   t = fmaf(x, t, 1.0f);
-  const float d = x < 0.3f ? x * t : 1.0f - q;
+  const float d = x < 0.15f ? x * t : 1.0f - q;
   const float r = (2.0f - d) * __builtin_amdgcn_rcpf(d);
-  const float small = __builtin_amdgcn_logf(r) * kLn2;
-  return x >= 1.386f ? big : small;
+  const float lg = __builtin_amdgcn_logf(r);
+  return x >= 2.0f ? big : lg;
 }
+
+// phi(x) / ln 2 for x in [0, inf]
+__device__ __forceinline__ float phi_to2(float x) {
+  x = fminf(x, 100.0f);  // phi(100) < 1e-43: the result is 0 either way
+  const float q = __builtin_amdgcn_exp2f(-x * kL2e);
+  return phi_core(x, q, 2.0f * kL2e);
+}
+
+// phi(y ln 2) for y in [0, inf]
+__device__ __forceinline__ float phi_from2(float y) {
+  y = fminf(y, 100.0f * kL2e);
+  const float q = __builtin_amdgcn_exp2f(-y);
+  const float v = phi_core(y * kLn2, q, 2.0f);
+  return y * kLn2 >= 2.0f ? v : v * kLn2;
+}
+
+// phi(x) in natural units
+__device__ __forceinline__ float phi(float x) { return phi_from2(x * kL2e); }
 
 __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLmax), kLmax); }
 
 // Check rule (Eq. 5) on one lane's incoming messages mv[0..dc) (already clamped):
 // E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from a
-// prefix and a suffix (no total-minus-self), sign_j = parity of the other signs.
+// prefix and a suffix (no total-minus-self).  sign_j is the product of the other
+// messages' signs, taken from the IEEE sign bits (as the tanh product would give it,
+// including the sign of zeros): the XOR of all sign bits with M_j's own.
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 template <int DC>
 __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   float ph[DMAX], pre[DMAX];
-  uint32_t sg = 0;
+  uint32_t sx = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      sg |= (mv[j] < 0.0f ? 1u : 0u) << j;
-      ph[j] = phi(fabsf(mv[j]));
+      sx ^= __float_as_uint(mv[j]);
+      ph[j] = phi_to2(fabsf(mv[j]));  // base-2 units
     }
   }
   float acc = 0.0f;
@@ -83,13 +100,13 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
       acc += ph[j];
     }
   }
-  const uint32_t tot = (uint32_t)__builtin_popcount(sg) & 1u;
   float suf = 0.0f;
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {
     if (FIXED || j < dc) {
-      const float mag = phi(pre[j] + suf);
-      eout[j] = (((sg >> j) ^ tot) & 1u) ? -mag : mag;
+      const float mag = phi_from2(pre[j] + suf);
+      const uint32_t sgn = (sx ^ __float_as_uint(mv[j])) & 0x80000000u;
+      eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
       suf += ph[j];
     }
   }
