@@ -268,12 +268,104 @@ def bench_c5(args, torch, P):
                                    "weights N(1, 0.1^2), mean BCE loss"}}
 
 
+def bench_paper(args, torch, P):
+    """Table I: Gallager bands n = 1032, 12 ones per row, 9 / 6 / 3 per column (rates 1/4, 1/2, 3/4),
+    1000 vectors per code, a preset 10 iterations.  Per-vector time (total time / vectors, as in
+    Figs. 4-5) for the plain, stream and batched forms and for the FP64 oracle at 1..N threads
+    splitting the vectors as the paper's batch processing does (Eq. 9)."""
+    import oracle
+    from synth import workloads as W
+
+    T, nvec = W.PAPER["iters"], W.PAPER["batch"]
+    codes = [W.code(nm) for nm in W.PAPER["codes"]]
+    graphs = [P.Graph.from_code(c) for c in codes]
+    words = [W.paper_words(i) for i in range(len(codes))]
+    llrs = [torch.from_numpy(w.llr).cuda() for w in words]
+    cws = [torch.from_numpy(w.cw).cuda() for w in words]
+    stream = torch.cuda.current_stream()
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
+
+    def outs(B, n):
+        return (torch.empty((B, n), dtype=torch.uint8, device="cuda"),
+                torch.empty((B, n), dtype=torch.float32, device="cuda"),
+                torch.empty((B,), dtype=torch.int32, device="cuda"))
+
+    per_code = []
+    for i, (c, g, x, cw) in enumerate(zip(codes, graphs, llrs, cws)):
+        ws = torch.empty(P.workspace_size(g, nvec), dtype=torch.uint8, device="cuda")
+        ws1 = torch.empty((256,), dtype=torch.uint8, device="cuda")
+        po, so, s1 = outs(nvec, c.n), outs(nvec, c.n), outs(1, c.n)
+        ms_p = time_launches(torch, lambda: P.decode(g, x, T, False, workspace=ws, out=po), args.steps, args.warmup,
+                             stream)
+        ms_s = time_launches(torch, lambda: P.decode_stream(g, x, T, False, workspace=ws1, out=so), args.steps,
+                             args.warmup, stream)
+        ms_1 = time_launches(torch, lambda: P.decode_stream(g, x[:1], T, False, workspace=ws1, out=s1),
+                             max(args.steps, 20), args.warmup, stream)
+        same = all(bool(torch.equal(a, b)) for a, b in zip(po, so))
+        errs = so[0] != cw
+        per_code.append({"code": c.name, "m": c.m, "n": c.n, "edges": c.nnz, "dv": c.nnz // c.n,
+                         "rate": W.rate(W.PAPER["codes"][i]),
+                         "plain_us_per_vector": avg(ms_p) * 1e3 / nvec,
+                         "stream_us_per_vector": avg(ms_s) * 1e3 / nvec,
+                         "stream_single_vector_us": avg(ms_1) * 1e3,
+                         "stream_edge_updates_per_s": nvec * T * c.nnz / (avg(ms_s) * 1e-3),
+                         "stream_equal_to_plain": same, "ber_coded": float(errs.float().mean().item()),
+                         "fer": float(errs.any(dim=1).float().mean().item())})
+        log(f"[bench] {c.name}: plain {avg(ms_p):.3f} ms, stream {avg(ms_s):.3f} ms, one vector {avg(ms_1):.3f} ms")
+
+    batch = P.Batch(graphs, llrs, T)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, False)
+    resolved, _ = batch.resolve(shape)
+    bws = batch.workspace(shape)
+    ms_b = time_launches(torch, lambda: batch.run(False, shape, bws), args.steps, args.warmup, stream)
+
+    sample = max(1, min(args.paper_cpu_sample, nvec))
+    top = oracle.default_threads()
+    sweep = []
+    nt = 1
+    while True:
+        row = {"threads": nt}
+        for i, c in enumerate(codes):
+            t0 = time.perf_counter()
+            oracle.decode(c, words[i].llr[:sample], T, False, nt)
+            row[c.name + "_us_per_vector"] = (time.perf_counter() - t0) * 1e6 / sample
+        sweep.append(row)
+        log(f"[bench] oracle {nt} threads: {row}")
+        if nt >= top:
+            break
+        nt = min(2 * nt, top)
+    last = sweep[-1]
+    cpu_us = avg([last[c.name + "_us_per_vector"] for c in codes])
+
+    total_vec = nvec * len(codes)
+    stream_us = avg([r["stream_us_per_vector"] for r in per_code])
+    bits = sum(c.n for c in codes) * nvec
+    return {"metric": "per-vector decode time, Table I codes (n=1032, 12 ones per row, 9/6/3 per column), "
+                      "10 iterations, 1000 vectors per code",
+            "value": stream_us, "unit": "us/vector", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": sum(r["stream_us_per_vector"] for r in per_code) * nvec / 1e3,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "Gallager bands n=1032, d_c=12, d_v in {9,6,3}; 1000 words per code at 3.0 dB; "
+                                   "10 iterations, no early stop", "form": "stream (mean over the three rates)"},
+            "per_code": per_code,
+            "batched_three_codes_one_launch": {"ms": avg(ms_b), "us_per_vector": avg(ms_b) * 1e3 / total_vec,
+                                               "coded_gbit_s": bits / (avg(ms_b) * 1e-3) / 1e9,
+                                               "shape": resolved.as_dict(len(codes))},
+            "stream_coded_gbit_s": bits / (sum(r["stream_us_per_vector"] for r in per_code) * nvec * 1e-6) / 1e9,
+            "cpu_baseline": {"value": cpu_us, "unit": "us/vector", "cores": top, "kind": "oracle",
+                             "sample": f"first {sample} vectors of each code, FP64 C oracle, 10 iterations, "
+                                       f"vectors split over threads as in Eq. 9",
+                             "thread_sweep": sweep, "cpu": platform.processor() or platform.machine()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "paper"],
                     help="c2: (3,6) n=4096 Eb/N0 sweep (default); c4: six-code mixed batch, batched vs per-code "
-                         "plain launches; c5: unrolled differentiable form, forward and forward+backward")
+                         "plain launches; c5: unrolled differentiable form, forward and forward+backward; "
+                         "paper: Table I codes, per-vector time")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=65536, help="words per Eb/N0 point")
@@ -281,6 +373,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the library's default shape")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paper-cpu-sample", type=int, default=64, help="vectors per code for the oracle thread sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling hardware byte counters)")
     args = ap.parse_args()
@@ -308,6 +401,9 @@ def main():
         return
     if args.workload == "c5":
         print(json.dumps(bench_c5(args, torch, P)), flush=True)
+        return
+    if args.workload == "paper":
+        print(json.dumps(bench_paper(args, torch, P)), flush=True)
         return
 
     code, ebn0s, llr, cw = make_inputs(args, torch)

@@ -118,9 +118,11 @@ ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *suppor
  * Same contract and bit-identical outputs as ldpc_decode, computed by the stream
  * form (Sec. III-B's spreading of one word over many workers, here the threads of
  * one workgroup with every message in LDS).  Persistent workgroups take words from
- * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024; 0 = by
- * code size).  workspace: >= 256 device bytes (the counter).  Returns
- * LDPC_ERR_UNSUPPORTED when the word state exceeds the LDS of one workgroup.
+ * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024, up to 512
+ * for codes outside the fixed degree pairs with a check degree above 8; 0 = by code
+ * size); a larger value returns LDPC_ERR_INVALID_ARG.  workspace: >= 256 device
+ * bytes (the counter).  Returns LDPC_ERR_UNSUPPORTED when the word state exceeds the
+ * LDS of one workgroup.
  */
 ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
                                uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,

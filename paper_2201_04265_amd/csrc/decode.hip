@@ -24,10 +24,10 @@
 namespace ldpc {
 
 template <int DC, int DV>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
-    plain_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
-                        int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard, float *__restrict__ post,
-                        int32_t *__restrict__ iters) {
+__device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__restrict__ llr32,
+                                                  const double *__restrict__ llr64, int B, int max_iters,
+                                                  int early_stop, char *ws, uint8_t *__restrict__ hard,
+                                                  float *__restrict__ post, int32_t *__restrict__ iters) {
   __shared__ float stage[TW][TW + 1];
   __shared__ unsigned long long unsat_w[16];
   const int lane = lane_id();
@@ -73,6 +73,30 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
   if (wave == 0 && lane < nvalid) iters[cw0 + lane] = my_iters;
 }
 
+// Low check degrees fit in 64 VGPRs, so the kernel can ask for 8 waves per SIMD (more
+// HBM requests in flight); higher degrees would spill their message arrays to scratch
+// under that limit and take the compiler's own register budget instead.
+template <int DC, int DV>
+constexpr bool plain_fits_8_waves() {
+  return DC > 0 ? DC <= 6 : -DC <= 8;
+}
+
+template <int DC, int DV>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
+    plain_decode_kernel_w8(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
+                           int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard,
+                           float *__restrict__ post, int32_t *__restrict__ iters) {
+  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters);
+}
+
+template <int DC, int DV>
+__global__ void __launch_bounds__(1024)
+    plain_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
+                        int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard, float *__restrict__ post,
+                        int32_t *__restrict__ iters) {
+  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters);
+}
+
 }  // namespace ldpc
 
 using namespace ldpc;
@@ -87,9 +111,17 @@ namespace {
 using PlainKernel = void (*)(GraphDev, const float *, const double *, int, int, int, char *, uint8_t *, float *,
                              int32_t *);
 
+template <int DC, int DV>
+PlainKernel plain_kernel_for() {
+  if constexpr (plain_fits_8_waves<DC, DV>())
+    return plain_decode_kernel_w8<DC, DV>;
+  else
+    return plain_decode_kernel<DC, DV>;
+}
+
 PlainKernel pick_plain(const ldpc_graph_s *g) {
   PlainKernel k = nullptr;
-#define LDPC_PICK(C, V) k = plain_decode_kernel<C, V>
+#define LDPC_PICK(C, V) k = plain_kernel_for<C, V>()
   LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
 #undef LDPC_PICK
   return k;

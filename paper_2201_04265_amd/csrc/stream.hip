@@ -26,8 +26,14 @@ __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
   return (size_t)nnz * 9 + (size_t)n * 8 + 16;
 }
 
+// Workgroup size limit per degree pair: the generic kernels for check degrees above 8
+// hold up to 32 messages per thread and would spill under the 128-VGPR budget of a
+// 1024-thread workgroup, so they are built for at most 512 threads (256 VGPRs).
+template <int DC>
+constexpr int kStreamMaxThreads = DC < -8 ? 512 : 1024;
+
 template <int DC, int DV>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     stream_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                          int max_iters, int early_stop, int *counter, uint8_t *__restrict__ hard,
                          float *__restrict__ post, int32_t *__restrict__ iters) {
@@ -150,18 +156,20 @@ namespace {
 using StreamKernel = void (*)(GraphDev, const float *, const double *, int, int, int, int *, uint8_t *, float *,
                               int32_t *);
 
-StreamKernel pick_stream(const ldpc_graph_s *g) {
+StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads) {
   StreamKernel k = nullptr;
-#define LDPC_PICK(C, V) k = stream_decode_kernel<C, V>
+#define LDPC_PICK(C, V)                    \
+  k = stream_decode_kernel<C, V>;          \
+  max_threads = kStreamMaxThreads<C>
   LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
 #undef LDPC_PICK
   return k;
 }
 
-int stream_threads(const ldpc_graph_s *g) {
+int stream_threads(const ldpc_graph_s *g, int max_threads) {
   const int big = std::max(g->m, g->n);
   int nt = 64;
-  while (nt < 1024 && nt * 2 <= big) nt *= 2;
+  while (nt < max_threads && nt * 2 <= big) nt *= 2;
   return nt;
 }
 }  // namespace
@@ -197,8 +205,12 @@ extern "C" ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32
   ldpc_status st = ldpc_stream_lds_bytes(g, &lds, &ok);
   if (st != LDPC_OK) return st;
   if (!ok) return set_error(LDPC_ERR_UNSUPPORTED, "word state (" + std::to_string(lds) + " bytes) exceeds LDS");
-  StreamKernel k = pick_stream(g);
-  const int nt = threads ? threads : stream_threads(g);
+  int max_threads = 1024;
+  StreamKernel k = pick_stream(g, max_threads);
+  if (threads > max_threads)
+    return set_error(LDPC_ERR_INVALID_ARG,
+                     "threads above " + std::to_string(max_threads) + " for this code's check degree");
+  const int nt = threads ? threads : stream_threads(g, max_threads);
   int dev = 0, cus = 0, per_cu = 0;
   LDPC_HIP_CHECK(hipGetDevice(&dev));
   LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

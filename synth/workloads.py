@@ -1,4 +1,4 @@
-"""The five synthetic workloads (codes, batch shapes, channel points), seeded.
+"""The synthetic workloads (codes, batch shapes, channel points), seeded.
 
 Config numbers:
   1  (3,6) n=96 Gallager band, 1000 words, 2.0 dB, FP64 LLRs, 20 iterations
@@ -6,6 +6,7 @@ Config numbers:
   3  quasi-cyclic 22x44 protograph lifted by Z=256 (n=11264), 16384 words, 1.5 dB, 30 iterations
   4  mixed batch of six codes, 4096 words round-robin, per-code Eb/N0 in [1, 4] dB, 50 iterations
   5  (3,6) n=1024, unrolled 10 iterations with per-edge weights N(1, 0.1^2), 4096 words, 2.0 dB
+  6  Table I: Gallager bands n=1032, d_c=12, d_v in {9, 6, 3}, 1000 words each, 3.0 dB, 10 iterations
 
 Every random draw comes from ``codes.rng_for(cfg, purpose, ...)`` with purpose
 0 = H, 1 = information bits, 2 = noise, 3 = weights, 4 = per-code Eb/N0.  Words
@@ -27,7 +28,7 @@ BLOCK = 1024
 
 @functools.lru_cache(maxsize=None)
 def code(name: str) -> codes.Code:
-    """Named codes of the five workloads (cached per process)."""
+    """Named codes of the workloads (cached per process)."""
     if name == "c1":
         return codes.gallager_band(96, 3, 6, codes.rng_for(1, 0), "band(3,6)n96")
     if name == "c2":
@@ -111,6 +112,10 @@ C3 = dict(code="c3", batch=16384, ebn0=1.5, max_iters=30, fp32=True, cfg=3)
 C4_CODES = tuple(f"c4_{i}" for i in range(6))
 C4 = dict(codes=C4_CODES, batch=4096, max_iters=50, fp32=True, cfg=4)
 C5 = dict(code="c5", batch=4096, ebn0=2.0, iters=10, fp32=True, cfg=5)
+# Table I of the paper: n = 1032, 12 ones per row, 9 / 6 / 3 per column (design rates 1/4, 1/2,
+# 3/4), 10 decoding iterations (a preset count, no early stop), 1000 vectors.  The paper gives no
+# channel point; at 3.0 dB the rate-1/2 and 3/4 codes decode some words and not others.
+PAPER = dict(codes=("paper_r14", "paper_r12", "paper_r34"), batch=1000, iters=10, ebn0=3.0, fp32=True, cfg=6)
 
 
 def c4_ebn0() -> np.ndarray:
@@ -127,3 +132,9 @@ def c4_counts(batch: int = 4096) -> list[int]:
 def c5_weights(T: int = 10) -> np.ndarray:
     E = code("c5").nnz
     return codes.rng_for(5, 3).normal(1.0, 0.1, size=(T, E)).astype(np.float32)
+
+
+def paper_words(i: int, count: int | None = None) -> Words:
+    """The Table I vectors of code i (0: rate 1/4, 1: 1/2, 2: 3/4)."""
+    return words(PAPER["codes"][i], PAPER["cfg"], 0, PAPER["ebn0"], 0, count or PAPER["batch"],
+                 fp32=PAPER["fp32"], code_key=i)

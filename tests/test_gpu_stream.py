@@ -108,3 +108,22 @@ def test_too_large_is_unsupported(P):
     with pytest.raises(P.LdpcError) as e:
         P.decode_stream(g, x, 10)
     assert e.value.status == -5
+
+
+def test_thread_limit_of_generic_high_degree_codes(P):
+    """Codes outside the fixed degree pairs with a check degree above 8 run at most 512 threads."""
+    rng = np.random.default_rng(77)
+    n, m = 300, 40
+    chk, var = [], []
+    for c in range(m):
+        vs = rng.choice(n, size=20, replace=False)
+        chk += [c] * 20
+        var += list(vs)
+    code = codes.from_edges(m, n, np.array(chk), np.array(var))
+    g = P.Graph.from_code(code)
+    x = torch.from_numpy(rng.normal(2.0, 2.0, size=(9, n)).astype(np.float32)).cuda()
+    with pytest.raises(P.LdpcError) as e:
+        P.decode_stream(g, x, 5, threads=1024)
+    assert e.value.status == -1
+    a, b = both(P, g, x.cpu().numpy(), 12, True, 512)
+    same(a, b)

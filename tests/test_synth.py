@@ -135,3 +135,19 @@ def test_blocks_regenerate_independently():
     b = workloads.words("c1", 1, 3, 2.0, 2047, 10, fp32=True)
     assert np.array_equal(a.llr[2047:2057], b.llr) and np.array_equal(a.cw[2047:2057], b.cw)
     assert a.llr.dtype == np.float32
+
+
+@pytest.mark.parametrize("i,dv,design_rate", [(0, 9, 0.25), (1, 6, 0.5), (2, 3, 0.75)])
+def test_table1_codes(oracle_lib, i, dv, design_rate):
+    """Table I: n = 1032, 12 ones per row, 9 / 6 / 3 per column, design rates 1/4, 1/2, 3/4."""
+    name = workloads.PAPER["codes"][i]
+    code = workloads.code(name)
+    assert (code.n, code.m) == (1032, 1032 * dv // 12)
+    assert np.all(code.row_degrees() == 12) and np.all(code.col_degrees() == dv)
+    assert 1 - code.m / code.n == design_rate
+    s = workloads.systematic(name)
+    assert s.k / s.n >= design_rate  # dependent rows only raise the rate
+    G = s.generator()
+    assert not np.any((code.dense().astype(np.int64) @ G.T.astype(np.int64)) & 1)
+    wd = workloads.paper_words(i, 50)
+    assert np.all(oracle_lib.syndrome_ok(code, wd.cw) == 1)
