@@ -46,9 +46,9 @@ COUNTER_TRAFFIC = {"sources_sha1": "af8949c8bf987d13f8e379c19e1d71d14e46e5d3", "
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
 # VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 316 VALU instructions per degree-6 check (36 of them quarter-rate transcendentals)
+# code: 115 VALU instructions per degree-6 check (18 of them quarter-rate exp2 / rcp / log2)
 # and 30 per degree-3 variable; a quarter-rate instruction occupies 4 issue slots.
-STREAM_VALU_SLOTS_PER_EDGE = (316 + 3 * 36) / 6.0 + 30 / 3.0
+STREAM_VALU_SLOTS_PER_EDGE = (115 + 3 * 18) / 6.0 + 30 / 3.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-operations per second, 1 slot each
 
 

@@ -18,96 +18,76 @@ constexpr float kLmax = 20.0f;  // saturation of variable-to-check messages
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// phi(x) = log((e^x + 1) / (e^x - 1)) = 2 atanh(e^-x) for x >= 0: the magnitude map
-// of the tanh rule, 2 atanh(prod tanh(a_i / 2)) = phi(sum phi(a_i)).  phi(0) = +inf
-// and phi(+inf) = 0, so a zero input message zeroes the others.
-// Evaluated from the hardware exp2 / log2 / reciprocal with two branch-free paths
-// (relative error below 1e-6 over [0, inf), below 4e-7 for x < 10):
-//   x >= 2 (q = e^-x <= 0.136): the odd series 2 atanh(q) = 2q (1 + q^2/3 + q^4/5 + q^6/7),
-//                               truncation < 2e-9;
-//   x <  2: phi = log((2 - d) / d) with d = 1 - e^-x, where d comes from the Taylor
-//           series x (1 - x/2 + x^2/6 - x^3/24 + x^4/120) for x < 0.15 (no cancellation)
-//           and from 1 - q above.
-// The check rule applies phi twice with a sum in between, so the inner sum is kept
-// in base-2 units (phi / ln 2): phi_to2 takes x and returns phi(x) / ln 2, phi_from2
-// takes y = x / ln 2 and returns phi(x).  e^-x = 2^(-x log2 e); the rounding of that
-// product only affects phi(x) for large x, where phi is tiny and only enters sums.
 constexpr float kL2e = 1.44269504088896341f;  // log2(e) = 1 / ln 2
 constexpr float kLn2 = 0.693147180559945309f;
-
-__device__ __forceinline__ float phi_core(float x, float q, float c) {
-  // x: argument, q = e^-x; returns c * phi(x) on the series path and the base-2
-  // logarithm of (2 - d) / d on the other (the caller scales it)
-  const float s = q * q;
-  float p = fmaf(s, c / 7.0f, c / 5.0f);
-  p = fmaf(s, p, c / 3.0f);
-  p = fmaf(s, p, c);
-  const float big = q * p;
-  float t = fmaf(x, 1.0f / 120.0f, -1.0f / 24.0f);
-  t = fmaf(x, t, 1.0f / 6.0f);
-  t = fmaf(x, t, -0.5f);
-  t = fmaf(x, t, 1.0f);
-  const float d = x < 0.15f ? x * t : 1.0f - q;
-  const float r = (2.0f - d) * __builtin_amdgcn_rcpf(d);
-  const float lg = __builtin_amdgcn_logf(r);
-  return x >= 2.0f ? big : lg;
-}
-
-// phi(x) / ln 2 for x in [0, inf]
-__device__ __forceinline__ float phi_to2(float x) {
-  x = fminf(x, 100.0f);  // phi(100) < 1e-43: the result is 0 either way
-  const float q = __builtin_amdgcn_exp2f(-x * kL2e);
-  return phi_core(x, q, 2.0f * kL2e);
-}
-
-// phi(y ln 2) for y in [0, inf]
-__device__ __forceinline__ float phi_from2(float y) {
-  y = fminf(y, 100.0f * kL2e);
-  const float q = __builtin_amdgcn_exp2f(-y);
-  const float v = phi_core(y * kLn2, q, 2.0f);
-  return y * kLn2 >= 2.0f ? v : v * kLn2;
-}
-
-// phi(x) in natural units
-__device__ __forceinline__ float phi(float x) { return phi_from2(x * kL2e); }
 
 __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLmax), kLmax); }
 
 // Check rule (Eq. 5) on one lane's incoming messages mv[0..dc) (already clamped):
-// E_j = sign_j * phi(sum_{i != j} phi(|M_i|)) with the exclusive sum built from a
-// prefix and a suffix (no total-minus-self).  sign_j is the product of the other
-// messages' signs, taken from the IEEE sign bits (as the tanh product would give it,
-// including the sign of zeros): the XOR of all sign bits with M_j's own.
+// E_j = sign_j * 2 atanh(prod_{i != j} tanh(|M_i| / 2)).
+//
+// Magnitudes.  With q_i = e^-|M_i|, tanh(|M_i| / 2) = (1 - q_i) / (1 + q_i), so a
+// product over a set of messages is B / A with A = prod (1 + q_i), B = prod (1 - q_i),
+// and 2 atanh(B / A) = ln((A + B) / (A - B)).  Each set is carried as the pair
+// d = (A - B) / 2, s = (A + B) / 2, which only ever adds non-negative terms:
+//   one message       (d, s) = (q, 1)            the empty set (0, 1)
+//   joining two sets  (d, s) = (d1 s2 + s1 d2, s1 s2 + d1 d2)
+// so neither a tanh near 1 (large |M|, where 1 - tanh cancels) nor one near 0 loses
+// the difference A - B, and the magnitude is ln(s / d): one exp2 per message and one
+// reciprocal and one log2 per output.  The pair of the other messages of edge j joins
+// a prefix pair (messages before j) and a suffix pair (after j).  |M_i| <= 20 keeps
+// q_i >= 2e-9 and d > 0; a zero message (q = 1) gives d = s and so a zero output on
+// the others.  Error of the FP32 magnitude: below 5.5e-7 max(|E|, 1) (an absolute
+// error for small outputs, a relative one above 1).
+//
+// Signs.  sign_j is the product of the other messages' signs, taken from the IEEE sign
+// bits (as the tanh product would give it, including the sign of zeros): the XOR of
+// all sign bits with M_j's own.
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 template <int DC>
 __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
-  float ph[DMAX], pre[DMAX];
+  // qs[j] = q_j with M_j's sign bit, so that the messages themselves are not kept
+  float qs[DMAX], pd[DMAX], ps[DMAX];
   uint32_t sx = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      sx ^= __float_as_uint(mv[j]);
-      ph[j] = phi_to2(fabsf(mv[j]));  // base-2 units
+      const uint32_t b = __float_as_uint(mv[j]);
+      sx ^= b;
+      const float q = __builtin_amdgcn_exp2f(-fabsf(mv[j]) * kL2e);
+      qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
     }
   }
-  float acc = 0.0f;
+  float d = 0.0f, s = 1.0f;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      pre[j] = acc;
-      acc += ph[j];
+      pd[j] = d;
+      ps[j] = s;
+      const float q = fabsf(qs[j]);
+      const float dn = fmaf(s, q, d);
+      s = fmaf(d, q, s);
+      d = dn;
     }
   }
-  float suf = 0.0f;
+  d = 0.0f;
+  s = 1.0f;
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {
     if (FIXED || j < dc) {
-      const float mag = phi_from2(pre[j] + suf);
-      const uint32_t sgn = (sx ^ __float_as_uint(mv[j])) & 0x80000000u;
-      eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
-      suf += ph[j];
+      const float od = fmaf(ps[j], d, pd[j] * s);
+      const float os = fmaf(ps[j], s, pd[j] * d);
+      const float mag = __builtin_amdgcn_logf(os * __builtin_amdgcn_rcpf(od)) * kLn2;
+      // rounding can put os / od a hair below 1 when the exact output is ~1e-7:
+      // keep the magnitude's sign bit out of the result
+      const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
+      eout[j] = __uint_as_float(sgn | (__float_as_uint(mag) & 0x7fffffffu));
+      const float q = fabsf(qs[j]);
+      const float dn = fmaf(s, q, d);
+      s = fmaf(d, q, s);
+      d = dn;
     }
   }
 }
