@@ -110,7 +110,7 @@ ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, i
 
 /* ---- stream form: one word per workgroup, state in LDS -------------------- */
 
-/* LDS bytes one word's decoding state needs (9 x edges + 8 x n) and whether it fits
+/* LDS bytes one word's decoding state needs (5 x edges + 4 x n) and whether it fits
  * one workgroup of the current device (*supported = 1). */
 ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported);
 
@@ -119,8 +119,9 @@ ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *suppor
  * form (Sec. III-B's spreading of one word over many workers, here the threads of
  * one workgroup with every message in LDS).  Persistent workgroups take words from
  * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024, up to 512
- * for codes outside the fixed degree pairs with a check degree above 8; 0 = by code
- * size); a larger value returns LDPC_ERR_INVALID_ARG.  workspace: >= 256 device
+ * for codes outside the fixed degree pairs with a check degree above 8; 0 = the size
+ * up to 512 that keeps the most threads resident); a larger value returns
+ * LDPC_ERR_INVALID_ARG.  The channel LLRs are read again in every iteration.  workspace: >= 256 device
  * bytes (the counter).  Returns LDPC_ERR_UNSUPPORTED when the word state exceeds the
  * LDS of one workgroup.
  */

@@ -60,6 +60,13 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
       qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
     }
   }
+  // Joins with the empty set (0, 1) are written out: they are exact, and 0 * x cannot
+  // be folded by the compiler.  A generic degree's last suffix step keeps the general
+  // form, which gives the same values.  A factor that is the constant 1 of a fresh
+  // pair in one instantiation and a computed 1.0 in another only ever appears in a
+  // plain product feeding an fma's addend (x * 1 rounds to x either way), never as an
+  // fma multiplicand: folding fma(a, 1, b * c) to a + b * c would let the compiler fuse
+  // b * c differently in the two, and fixed and generic degrees must agree bit for bit.
   float d = 0.0f, s = 1.0f;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
@@ -67,9 +74,14 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
       pd[j] = d;
       ps[j] = s;
       const float q = fabsf(qs[j]);
-      const float dn = fmaf(s, q, d);
-      s = fmaf(d, q, s);
-      d = dn;
+      if (j == 0) {
+        d = q;
+        s = 1.0f;
+      } else {
+        const float dn = fmaf(s, q, d);
+        s = fmaf(d, q, s);
+        d = dn;
+      }
     }
   }
   d = 0.0f;
@@ -77,17 +89,31 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {
     if (FIXED || j < dc) {
-      const float od = fmaf(ps[j], d, pd[j] * s);
-      const float os = fmaf(ps[j], s, pd[j] * d);
-      const float mag = __builtin_amdgcn_logf(os * __builtin_amdgcn_rcpf(od)) * kLn2;
-      // rounding can put os / od a hair below 1 when the exact output is ~1e-7:
-      // keep the magnitude's sign bit out of the result
+      const bool top = FIXED && j == DMAX - 1;  // empty suffix
+      float od, os;
+      if (j == 0) {
+        od = d;
+        os = s;
+      } else if (top) {
+        od = pd[j];
+        os = ps[j];
+      } else {
+        od = fmaf(ps[j], d, pd[j] * s);
+        os = fmaf(pd[j], d, ps[j] * s);
+      }
+      // |log2|: rounding can put os / od a hair below 1 when the exact output is ~1e-7
+      const float mag = fabsf(__builtin_amdgcn_logf(os * __builtin_amdgcn_rcpf(od))) * kLn2;
       const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
-      eout[j] = __uint_as_float(sgn | (__float_as_uint(mag) & 0x7fffffffu));
+      eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
       const float q = fabsf(qs[j]);
-      const float dn = fmaf(s, q, d);
-      s = fmaf(d, q, s);
-      d = dn;
+      if (top) {
+        d = q;
+        s = 1.0f;
+      } else {
+        const float dn = fmaf(s, q, d);
+        s = fmaf(d, q, s);
+        d = dn;
+      }
     }
   }
 }
@@ -117,6 +143,24 @@ __device__ __forceinline__ int check_update(const float *__restrict__ Mt, float 
   for (int j = 0; j < DMAX; ++j)
     if ((FIXED || j < dc) && store) Et[(e0 + j) * TW + lane] = ev[j];
   return (int)((zx >> lane) & 1ull);
+}
+
+// Exclusive sums of Eq. 6 as prefix + suffix: emit(j, pre[j] + sum_{i > j} ev[i]), where
+// pre[j] = R_v + sum_{i < j} ev[i].  The last message's suffix is empty and adds nothing
+// (emit gets pre exactly).  DV as DC above; every form of the decoder uses this order.
+template <int DV, typename Emit>
+__device__ __forceinline__ void var_exclusive(const float *pre, const float *ev, int dv, Emit &&emit) {
+  constexpr int DMAX = DV > 0 ? DV : -DV;
+  constexpr bool FIXED = DV > 0;
+  float suf = 0.0f;
+#pragma unroll
+  for (int j = DMAX - 1; j >= 0; --j) {
+    if (FIXED || j < dv) {
+      const bool last = FIXED ? j == DMAX - 1 : j == dv - 1;
+      emit(j, last ? pre[j] : pre[j] + suf);
+      suf = last ? ev[j] : suf + ev[j];
+    }
+  }
 }
 
 // Posterior of one variable (Eq. 7): R_v + the incoming c->v messages in ascending
@@ -171,14 +215,7 @@ __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const f
   }
   const unsigned long long z = __ballot(L <= 0.0f);
   if (lane == 0) Zt[v] = z;
-  float suf = 0.0f;
-#pragma unroll
-  for (int j = DMAX - 1; j >= 0; --j) {
-    if (FIXED || j < dv) {
-      if (store) Mt[eid[j] * TW + lane] = clamp_msg(pre[j] + suf);
-      suf += ev[j];
-    }
-  }
+  if (store) var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { Mt[eid[j] * TW + lane] = clamp_msg(x); });
 }
 
 }  // namespace ldpc

@@ -1,4 +1,4 @@
-// Stream form: one word per workgroup, the whole decoding state in LDS.
+// Stream form: one word per workgroup, the decoding state in LDS.
 //
 // Sec. III-B spreads one word's Tanner graph over many workers ("stream
 // processing") and finds the exchange of messages between workers, every
@@ -10,20 +10,26 @@
 // the next word from an atomic counter when theirs stops, so a word that needs
 // few iterations never waits for another.
 //
-// LDS per word (all indexed in check-major edge order):
-//   M  [nnz] FP32 v->c messages (Eq. 6, clamped)    E [nnz] FP32 c->v messages (Eq. 5)
-//   Z  [nnz] u8   decision of each edge's variable   R, L [n] FP32 channel LLRs, posterior
+// LDS per word (indexed in check-major edge order):
+//   X [nnz] FP32  one message per edge, updated in place: the check phase reads the
+//                 v->c message (Eq. 6, clamped) and leaves the c->v message (Eq. 5);
+//                 the variable phase reads that and leaves the next v->c message.
+//                 Each edge is touched by its own check, then by its own variable.
+//   L [n]   FP32  posterior of the last variable phase (Eq. 7)
+//   Z [nnz] u8    decision of each edge's variable (Eq. 8)
+// The channel LLRs are re-read from the caller's buffer in every variable phase
+// (a coalesced read that stays in L2), which keeps a (3,6) n=4096 word at 77 KB so
+// that two words share a compute unit and one's barriers overlap the other's work.
 // The check phase tests the syndrome of the decisions it reads (Eq. 1) while it
-// computes new messages; the posterior of the last variable phase stays in L.
-// Per edge the arithmetic and its order are those of the plain decoder, so the
-// outputs are identical to it bit for bit.
+// computes new messages.  Per edge the arithmetic and its order are those of the
+// plain decoder, so the outputs are identical to it bit for bit.
 #include "internal.h"
 #include "tile.h"
 
 namespace ldpc {
 
 __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
-  return (size_t)nnz * 9 + (size_t)n * 8 + 16;
+  return (size_t)nnz * 5 + (size_t)n * 4 + 16;
 }
 
 // Workgroup size limit per degree pair: the generic kernels for check degrees above 8
@@ -41,12 +47,12 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
   constexpr int DVM = DV > 0 ? DV : -DV;
   extern __shared__ float smem[];
   __shared__ int s_word;
-  float *Mv = smem;
-  float *Ec = Mv + g.nnz;
-  float *R = Ec + g.nnz;
-  float *L = R + g.n;
+  __shared__ int s_unsat[16];  // per wavefront: some check of the word is unsatisfied
+  float *X = smem;
+  float *L = X + g.nnz;
   uint8_t *Zb = (uint8_t *)(L + g.n);
   const int t = threadIdx.x, NT = blockDim.x;
+  const int wave = wave_id(), W = NT >> 6;
   const size_t n = (size_t)g.n;
 
   for (;;) {
@@ -54,12 +60,11 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     __syncthreads();
     const int word = s_word;
     if (word >= B) break;  // same value in every thread
+    const size_t base = (size_t)word * n;
 
-    // ingest: R = L = channel LLRs, first messages M = clamp(R), channel decisions
+    // ingest: L = channel LLRs, first messages X = clamp(R), channel decisions
     for (int v = t; v < g.n; v += NT) {
-      const size_t off = (size_t)word * n + (size_t)v;
-      const float x = llr64 ? (float)llr64[off] : llr32[off];
-      R[v] = x;
+      const float x = llr64 ? (float)llr64[base + v] : llr32[base + v];
       L[v] = x;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
@@ -67,7 +72,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       const uint8_t z = x <= 0.0f ? 1 : 0;
       for (int j = 0; j < dv; ++j) {
         const int e = g.var_edges[p0 + j];
-        Mv[e] = mx;
+        X[e] = mx;
         Zb[e] = z;
       }
     }
@@ -84,29 +89,33 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
 #pragma unroll
         for (int j = 0; j < DCM; ++j) {
           if (DC > 0 || j < dc) {
-            mv[j] = Mv[e0 + j];
+            mv[j] = X[e0 + j];
             par ^= Zb[e0 + j];
           }
         }
         check_core<DC>(mv, dc, ev);
 #pragma unroll
         for (int j = 0; j < DCM; ++j)
-          if (DC > 0 || j < dc) Ec[e0 + j] = ev[j];
+          if (DC > 0 || j < dc) X[e0 + j] = ev[j];
         unsat |= par;
       }
-      const int any_unsat = __syncthreads_or(unsat);
+      const unsigned long long b = __ballot(unsat);
+      if ((t & 63) == 0) s_unsat[wave] = b != 0ull;
+      __syncthreads();
+      int any_unsat = 0;
+      for (int w = 0; w < W; ++w) any_unsat |= s_unsat[w];
       if ((early_stop && !any_unsat) || it == max_iters) break;  // same value in every thread
       for (int v = t; v < g.n; v += NT) {
         int p0, dv;
         var_range<DV>(g, v, p0, dv);
         float ev[DVM], pre[DVM];
         int eid[DVM];
-        const float r = R[v];
+        const float r = llr64 ? (float)llr64[base + v] : llr32[base + v];
 #pragma unroll
         for (int j = 0; j < DVM; ++j) {
           if (DV > 0 || j < dv) {
             eid[j] = g.var_edges[p0 + j];
-            ev[j] = Ec[eid[j]];
+            ev[j] = X[eid[j]];
           }
         }
         float acc = r;
@@ -119,28 +128,22 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         }
         L[v] = acc;
         const uint8_t z = acc <= 0.0f ? 1 : 0;
-        float suf = 0.0f;
-#pragma unroll
-        for (int j = DVM - 1; j >= 0; --j) {
-          if (DV > 0 || j < dv) {
-            Mv[eid[j]] = clamp_msg(pre[j] + suf);
-            Zb[eid[j]] = z;
-            suf += ev[j];
-          }
-        }
+        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) {
+          X[eid[j]] = clamp_msg(x);
+          Zb[eid[j]] = z;
+        });
       }
-      __syncthreads();
+      __syncthreads();  // also orders this iteration's reads of s_unsat before the next writes
       ++it;
     }
 
     for (int v = t; v < g.n; v += NT) {
       const float x = L[v];
-      const size_t off = (size_t)word * n + (size_t)v;
-      post[off] = x;
-      hard[off] = x <= 0.0f ? 1 : 0;
+      post[base + v] = x;
+      hard[base + v] = x <= 0.0f ? 1 : 0;
     }
     if (t == 0) iters[word] = it;
-    __syncthreads();  // L and s_word are reused by the next word
+    __syncthreads();  // L, s_word and s_unsat are reused by the next word
   }
 }
 
@@ -166,11 +169,38 @@ StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads) {
   return k;
 }
 
-int stream_threads(const ldpc_graph_s *g, int max_threads) {
+// Default workgroup size: the one that keeps the most threads resident per compute
+// unit (LDS and registers both limit it), from 64 up to the power of two covering the
+// larger of m and n but not above 512; on a tie the larger workgroup.  A batch smaller
+// than the resident capacity is counted at its own size.  Above 512 threads the cost
+// of bringing every wave to each of the two barriers per iteration outweighs the
+// shorter phases: 512 beat 1024 on (3,6) n=4096 both in throughput (by ~5 %) and for
+// a single word, and on the n=1032 Table I codes.
+constexpr int kStreamDefaultMaxThreads = 512;
+
+ldpc_status stream_threads(const ldpc_graph_s *g, StreamKernel k, int max_threads, size_t lds, int cus,
+                           int32_t batch, int &best_nt, int &best_per_cu) {
   const int big = std::max(g->m, g->n);
-  int nt = 64;
-  while (nt < max_threads && nt * 2 <= big) nt *= 2;
-  return nt;
+  const int cap = std::min(max_threads, kStreamDefaultMaxThreads);
+  int top = 64;
+  while (top < cap && top < big) top *= 2;
+  best_nt = 0;
+  best_per_cu = 0;
+  long best = -1;
+  for (int nt = top; nt >= 64; nt /= 2) {
+    int per_cu = 0;
+    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
+    if (per_cu < 1) continue;
+    const long groups = std::min<long>((long)per_cu * cus, batch);
+    const long score = groups * nt;
+    if (score > best) {
+      best = score;
+      best_nt = nt;
+      best_per_cu = per_cu;
+    }
+  }
+  if (best_nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  return LDPC_OK;
 }
 }  // namespace
 
@@ -210,13 +240,17 @@ extern "C" ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32
   if (threads > max_threads)
     return set_error(LDPC_ERR_INVALID_ARG,
                      "threads above " + std::to_string(max_threads) + " for this code's check degree");
-  const int nt = threads ? threads : stream_threads(g, max_threads);
-  int dev = 0, cus = 0, per_cu = 0;
+  int dev = 0, cus = 0, per_cu = 0, nt = threads;
   LDPC_HIP_CHECK(hipGetDevice(&dev));
   LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
-  if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  if (nt == 0) {
+    st = stream_threads(g, k, max_threads, lds, cus, batch, nt, per_cu);
+    if (st != LDPC_OK) return st;
+  } else {
+    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
+    if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  }
   const int grid = std::min(batch, cus * per_cu);
   int *counter = (int *)workspace;
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, counter);

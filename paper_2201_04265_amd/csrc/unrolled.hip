@@ -156,14 +156,7 @@ __global__ void __launch_bounds__(512)
         }
       }
       if (t < T) {
-        float suf = 0.0f;
-#pragma unroll
-        for (int j = DVM - 1; j >= 0; --j) {
-          if (DV > 0 || j < dv) {
-            An[eid[j] * TW + lane] = pre[j] + suf;
-            suf += ev[j];
-          }
-        }
+        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { An[eid[j] * TW + lane] = x; });
       } else {
         st.R[v * TW + lane] = acc;  // posterior replaces R after the last iteration
       }
