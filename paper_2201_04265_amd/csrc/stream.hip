@@ -38,6 +38,52 @@ __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
 template <int DC>
 constexpr int kStreamMaxThreads = DC < -8 ? 512 : 1024;
 
+// A check's messages are contiguous (edge e0 = c * DC for a fixed degree), so a row is
+// moved with 16- or 8-byte LDS accesses when DC allows: a check's row then starts on
+// a multiple of its access width, and consecutive threads' rows fall on disjoint banks.
+template <int DC>
+__device__ __forceinline__ void lds_row_load(const float *row, int dc, float *v) {
+  if constexpr (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 4; ++h) {
+      const float4 x = reinterpret_cast<const float4 *>(row)[h];
+      v[4 * h] = x.x;
+      v[4 * h + 1] = x.y;
+      v[4 * h + 2] = x.z;
+      v[4 * h + 3] = x.w;
+    }
+  } else if constexpr (DC > 0 && DC % 2 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 2; ++h) {
+      const float2 x = reinterpret_cast<const float2 *>(row)[h];
+      v[2 * h] = x.x;
+      v[2 * h + 1] = x.y;
+    }
+  } else {
+    constexpr int DM = DC > 0 ? DC : -DC;
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+      if (DC > 0 || j < dc) v[j] = row[j];
+  }
+}
+
+template <int DC>
+__device__ __forceinline__ void lds_row_store(float *row, int dc, const float *v) {
+  if constexpr (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 4; ++h)
+      reinterpret_cast<float4 *>(row)[h] = make_float4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+  } else if constexpr (DC > 0 && DC % 2 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 2; ++h) reinterpret_cast<float2 *>(row)[h] = make_float2(v[2 * h], v[2 * h + 1]);
+  } else {
+    constexpr int DM = DC > 0 ? DC : -DC;
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+      if (DC > 0 || j < dc) row[j] = v[j];
+  }
+}
+
 template <int DC, int DV>
 __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     stream_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
@@ -45,7 +91,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
                          float *__restrict__ post, int32_t *__restrict__ iters) {
   constexpr int DCM = DC > 0 ? DC : -DC;
   constexpr int DVM = DV > 0 ? DV : -DV;
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   __shared__ int s_word;
   __shared__ int s_unsat[16];  // per wavefront: some check of the word is unsatisfied
   float *X = smem;
@@ -86,17 +132,12 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         check_range<DC>(g, c, e0, dc);
         float mv[DCM], ev[DCM];
         int par = 0;
-#pragma unroll
-        for (int j = 0; j < DCM; ++j) {
-          if (DC > 0 || j < dc) {
-            mv[j] = X[e0 + j];
-            par ^= Zb[e0 + j];
-          }
-        }
-        check_core<DC>(mv, dc, ev);
+        lds_row_load<DC>(X + e0, dc, mv);
 #pragma unroll
         for (int j = 0; j < DCM; ++j)
-          if (DC > 0 || j < dc) X[e0 + j] = ev[j];
+          if (DC > 0 || j < dc) par ^= Zb[e0 + j];
+        check_core<DC>(mv, dc, ev);
+        lds_row_store<DC>(X + e0, dc, ev);
         unsat |= par;
       }
       const unsigned long long b = __ballot(unsat);
@@ -105,19 +146,31 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       int any_unsat = 0;
       for (int w = 0; w < W; ++w) any_unsat |= s_unsat[w];
       if ((early_stop && !any_unsat) || it == max_iters) break;  // same value in every thread
+      // The global reads of a variable (its edge list, its channel LLR) are issued one
+      // variable ahead, so their latency overlaps the LDS work of the current one.
+      int eidn[DVM], dvn = 0;
+      float rn = 0.0f;
+      auto fetch = [&](int vv) {
+        int p0;
+        var_range<DV>(g, vv, p0, dvn);
+        rn = llr64 ? (float)llr64[base + vv] : llr32[base + vv];
+#pragma unroll
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dvn) eidn[j] = g.var_edges[p0 + j];
+      };
+      if (t < g.n) fetch(t);
       for (int v = t; v < g.n; v += NT) {
-        int p0, dv;
-        var_range<DV>(g, v, p0, dv);
+        const int dv = dvn;
+        const float r = rn;
         float ev[DVM], pre[DVM];
         int eid[DVM];
-        const float r = llr64 ? (float)llr64[base + v] : llr32[base + v];
 #pragma unroll
-        for (int j = 0; j < DVM; ++j) {
-          if (DV > 0 || j < dv) {
-            eid[j] = g.var_edges[p0 + j];
-            ev[j] = X[eid[j]];
-          }
-        }
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dv) eid[j] = eidn[j];
+        if (v + NT < g.n) fetch(v + NT);
+#pragma unroll
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dv) ev[j] = X[eid[j]];
         float acc = r;
 #pragma unroll
         for (int j = 0; j < DVM; ++j) {
