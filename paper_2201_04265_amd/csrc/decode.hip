@@ -6,16 +6,19 @@
 // interleaved way of Algorithm 1 (check c and variable v go to wave c mod W and
 // v mod W), with a workgroup barrier where Algorithm 1 exchanges messages.
 //
-// HBM state of a tile (all FP32 [index][64] unless noted):
-//   M  [nnz]  v->c messages (Eq. 6, clamped)       R [n]  channel LLRs (Eq. 4)
+// HBM state of a tile (all FP32 [index][64]):
+//   M  [nnz]  v->c messages (Eq. 6, clamped), stored as M / 16 with the decision z_v
+//             (Eq. 8) in the exponent's top bit
 //   E0/E1 [nnz] c->v messages of even / odd iterations (Eq. 5)
-//   Z  [n] u64 decision masks, bit l = z_v of lane l's word (Eq. 8)
+//   R  [n]  channel LLRs (Eq. 4)
 // Iteration t+1 (flooding, Algorithm 1):
-//   check phase     every check: syndrome bit of z^(t), E^(t+1) from M^(t+1) into E[(t+1)&1]
+//   check phase     every check: syndrome bit of z^(t) (the XOR of its messages' bit 30),
+//                   E^(t+1) from M^(t+1) into E[(t+1)&1]
 //   decide          a lane whose z^(t) satisfies H z^T = 0 (Eq. 1), or with t = max_iters,
 //                   stops at t; from then on nothing of it is written, so its E^(t) stays
 //                   in E[t&1]
-//   variable phase  every variable: L^(t+1) (Eq. 7) -> Z, and M^(t+2) (Eq. 6) for running lanes
+//   variable phase  every variable: L^(t+1) (Eq. 7), and M^(t+2) (Eq. 6) carrying z^(t+1)
+//                   for running lanes
 // The egress recomputes each word's final posterior from its own E buffer with the
 // same summation as the variable phase, so it equals the L whose decisions stopped it.
 #include "internal.h"
@@ -48,7 +51,7 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
     for (int c = wave; c < g.m; c += W) {
       int e0, dc;
       check_range<DC>(g, c, e0, dc);
-      unsat |= check_update<DC>(st.M, En, st.Z, g.col_idx, e0, dc, lane, active);
+      unsat |= check_update<DC>(st.M, En, e0, dc, lane, active);
     }
     const unsigned long long b = __ballot(unsat);
     if (lane == 0) unsat_w[wave] = b;
@@ -64,7 +67,7 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
     for (int v = wave; v < g.n; v += W) {
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      var_update<DV>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, active);
+      var_update<DV>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, active);
     }
     __syncthreads();
   }

@@ -13,7 +13,7 @@
 // the word.
 //
 // Step G of a slot: check phase writes E into E[(G+1)&1] and tests the
-// syndrome of the decisions Z; lanes that stop at G have their last messages in
+// syndrome of the decisions the messages carry; lanes that stop at G have their last messages in
 // E[G&1] (all lanes of a slot share the step parity, so buffer choice is uniform).
 #include "internal.h"
 #include "multi.h"
@@ -71,7 +71,7 @@ __device__ __forceinline__ void slot_var_phase(const GraphDev &g, TileState st, 
   for (int v = wave; v < g.n; v += W) {
     int p0, dv;
     var_range<DV>(g, v, p0, dv);
-    var_update<DV, true>(st.R, En, st.M, st.Z, g.var_edges, p0, dv, v, lane, running || fresh, fresh);
+    var_update<DV, true>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, running || fresh, fresh);
   }
 }
 
@@ -108,7 +108,7 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
     for (int c = wave; c < g.m; c += W) {
       int e0, dc;
       check_range<DC>(g, c, e0, dc);
-      unsat |= check_update<DC>(st.M, En, st.Z, g.col_idx, e0, dc, lane, active);
+      unsat |= check_update<DC>(st.M, En, e0, dc, lane, active);
     }
     const unsigned long long b = __ballot(unsat);
     if (lane == 0) unsat_w[wave] = b;

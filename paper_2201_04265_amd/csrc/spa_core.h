@@ -23,6 +23,21 @@ constexpr float kLn2 = 0.693147180559945309f;
 
 __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLmax), kLmax); }
 
+// Hard decisions travel with the messages.  A v->c message M (Eq. 6, |M| <= 20) is
+// stored as M / 16: exact (a power of two), and |M / 16| <= 1.25 < 2 keeps the top
+// exponent bit (bit 30) at 0, so that bit carries the sending variable's decision
+// z_v = [L_v <= 0] (Eq. 8) without changing the message's value.  A check reads its
+// variables' decisions together with their messages, and its syndrome bit (Eq. 1) is
+// the XOR of those bits: no decision arrays and no extra loads.  The check rule takes
+// the stored form directly (the 1/16 folds into its first multiply).
+constexpr float kMsgDown = 0.0625f;
+constexpr uint32_t kDecisionBit = 1u << 30;
+
+// Stored v->c message from the pre-clamp value x, carrying decision z.
+__device__ __forceinline__ float v2c_store(float x, bool z) {
+  return __uint_as_float(__float_as_uint(clamp_msg(x) * kMsgDown) | (z ? kDecisionBit : 0u));
+}
+
 // Check rule (Eq. 5) on one lane's incoming messages mv[0..dc) (already clamped):
 // E_j = sign_j * 2 atanh(prod_{i != j} tanh(|M_i| / 2)).
 //
@@ -43,9 +58,14 @@ __device__ __forceinline__ float clamp_msg(float x) { return fminf(fmaxf(x, -kLm
 // Signs.  sign_j is the product of the other messages' signs, taken from the IEEE sign
 // bits (as the tanh product would give it, including the sign of zeros): the XOR of
 // all sign bits with M_j's own.
+// STORED: mv holds stored messages (M / 16 with a decision in bit 30, see v2c_store);
+// otherwise plain values M.  Both give the same outputs bit for bit: (M / 16) times
+// 16 log2(e) rounds exactly as M times log2(e).  Returns the XOR of the input bit
+// patterns: bit 31 is the sign of the product of all messages, and for stored
+// messages bit 30 is the parity of the decisions they carry (syndrome_bit).
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
-template <int DC>
-__device__ __forceinline__ void check_core(const float *mv, int dc, float *eout) {
+template <int DC, bool STORED = false>
+__device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *eout) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   // qs[j] = q_j with M_j's sign bit, so that the messages themselves are not kept
@@ -56,7 +76,8 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
     if (FIXED || j < dc) {
       const uint32_t b = __float_as_uint(mv[j]);
       sx ^= b;
-      const float q = __builtin_amdgcn_exp2f(-fabsf(mv[j]) * kL2e);
+      const float q = STORED ? __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown))
+                             : __builtin_amdgcn_exp2f(-fabsf(mv[j]) * kL2e);
       qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
     }
   }
@@ -116,33 +137,30 @@ __device__ __forceinline__ void check_core(const float *mv, int dc, float *eout)
       }
     }
   }
+  return sx;
 }
 
+// Syndrome bit of a check from the value check_core returned for stored messages.
+__device__ __forceinline__ int syndrome_bit(uint32_t sx) { return (int)((sx >> 30) & 1u); }
+
 // Check-node update of one check for the 64 words of a tile.
-//   Mt: v->c messages [nnz][64] (clamped); Et: new c->v messages [nnz][64];
-//   Zt: hard-decision masks [n] (bit l = decision of lane l's word).
+//   Mt: stored v->c messages [nnz][64] (v2c_store); Et: new c->v messages.
 // Returns the parity of the decisions over the check: the syndrome bit (Eq. 1) of
-// the decisions the incoming messages were computed with.
+// the decisions the incoming messages were sent with.
 template <int DC>
-__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et,
-                                            const unsigned long long *Zt, const int32_t *__restrict__ col_idx,
-                                            int e0, int dc, int lane, bool store) {
+__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et, int e0, int dc,
+                                            int lane, bool store) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   float mv[DMAX], ev[DMAX];
-  unsigned long long zx = 0;
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) {
-    if (FIXED || j < dc) {
-      mv[j] = Mt[(e0 + j) * TW + lane];
-      zx ^= Zt[col_idx[e0 + j]];
-    }
-  }
-  check_core<DC>(mv, dc, ev);
+  for (int j = 0; j < DMAX; ++j)
+    if (FIXED || j < dc) mv[j] = Mt[(e0 + j) * TW + lane];
+  const uint32_t sx = check_core<DC, true>(mv, dc, ev);
 #pragma unroll
   for (int j = 0; j < DMAX; ++j)
     if ((FIXED || j < dc) && store) Et[(e0 + j) * TW + lane] = ev[j];
-  return (int)((zx >> lane) & 1ull);
+  return syndrome_bit(sx);
 }
 
 // Exclusive sums of Eq. 6 as prefix + suffix: emit(j, pre[j] + sum_{i > j} ev[i]), where
@@ -190,17 +208,15 @@ __device__ __forceinline__ float var_posterior(float r, const float *__restrict_
   return acc;
 }
 
-// Variable-node update: posterior L (Eq. 7) -> decision mask Zt[v] (Eq. 8, z = [L <= 0]),
-// and the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6) as prefix + suffix.
-// With ZERO_E, lanes with `fresh` set see all incoming messages as 0 (a word that has
-// not been through a check phase yet): M = clamp(R), z = [R <= 0].
+// Variable-node update: posterior L (Eq. 7), its decision z = [L <= 0] (Eq. 8), and
+// the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6) as prefix + suffix,
+// stored carrying z.  With ZERO_E, lanes with `fresh` set see all incoming messages as 0
+// (a word that has not been through a check phase yet): M = clamp(R), z = [R <= 0].
 template <int DV, bool ZERO_E = false>
 __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const float *__restrict__ Et,
-                                           float *__restrict__ Mt, unsigned long long *Zt,
-                                           const int32_t *__restrict__ var_edges, int p0, int dv, int v, int lane,
-                                           bool store, bool fresh = false) {
+                                           float *__restrict__ Mt, const int32_t *__restrict__ var_edges, int p0,
+                                           int dv, int v, int lane, bool store, bool fresh = false) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
-  constexpr bool FIXED = DV > 0;
   float ev[DMAX], pre[DMAX];
   int eid[DMAX];
   const float r = Rt[v * TW + lane];
@@ -213,9 +229,9 @@ __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const f
     }
     L = r;
   }
-  const unsigned long long z = __ballot(L <= 0.0f);
-  if (lane == 0) Zt[v] = z;
-  if (store) var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { Mt[eid[j] * TW + lane] = clamp_msg(x); });
+  const bool z = L <= 0.0f;
+  if (store)
+    var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { Mt[eid[j] * TW + lane] = v2c_store(x, z); });
 }
 
 }  // namespace ldpc

@@ -12,24 +12,24 @@
 //
 // LDS per word (indexed in check-major edge order):
 //   X [nnz] FP32  one message per edge, updated in place: the check phase reads the
-//                 v->c message (Eq. 6, clamped) and leaves the c->v message (Eq. 5);
-//                 the variable phase reads that and leaves the next v->c message.
-//                 Each edge is touched by its own check, then by its own variable.
+//                 v->c message (Eq. 6, clamped; stored with its variable's decision) and
+//                 leaves the c->v message (Eq. 5); the variable phase reads that and
+//                 leaves the next v->c message.  Each edge is touched by its own
+//                 check, then by its own variable.
 //   L [n]   FP32  posterior of the last variable phase (Eq. 7)
-//   Z [nnz] u8    decision of each edge's variable (Eq. 8)
 // The channel LLRs are re-read from the caller's buffer in every variable phase
-// (a coalesced read that stays in L2), which keeps a (3,6) n=4096 word at 77 KB so
+// (a coalesced read that stays in L2), which keeps a (3,6) n=4096 word at 64 KB so
 // that two words share a compute unit and one's barriers overlap the other's work.
-// The check phase tests the syndrome of the decisions it reads (Eq. 1) while it
-// computes new messages.  Per edge the arithmetic and its order are those of the
-// plain decoder, so the outputs are identical to it bit for bit.
+// The check phase tests the syndrome of the decisions its messages carry (Eq. 1)
+// while it computes new messages.  Per edge the arithmetic and its order are those
+// of the plain decoder, so the outputs are identical to it bit for bit.
 #include "internal.h"
 #include "tile.h"
 
 namespace ldpc {
 
 __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
-  return (size_t)nnz * 5 + (size_t)n * 4 + 16;
+  return (size_t)nnz * 4 + (size_t)n * 4 + 16;
 }
 
 // Workgroup size limit per degree pair: the generic kernels for check degrees above 8
@@ -96,7 +96,6 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
   __shared__ int s_unsat[16];  // per wavefront: some check of the word is unsatisfied
   float *X = smem;
   float *L = X + g.nnz;
-  uint8_t *Zb = (uint8_t *)(L + g.n);
   const int t = threadIdx.x, NT = blockDim.x;
   const int wave = wave_id(), W = NT >> 6;
   const size_t n = (size_t)g.n;
@@ -114,13 +113,8 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       L[v] = x;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      const float mx = clamp_msg(x);
-      const uint8_t z = x <= 0.0f ? 1 : 0;
-      for (int j = 0; j < dv; ++j) {
-        const int e = g.var_edges[p0 + j];
-        X[e] = mx;
-        Zb[e] = z;
-      }
+      const float mx = v2c_store(x, x <= 0.0f);
+      for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = mx;
     }
     __syncthreads();
 
@@ -131,14 +125,10 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         int e0, dc;
         check_range<DC>(g, c, e0, dc);
         float mv[DCM], ev[DCM];
-        int par = 0;
         lds_row_load<DC>(X + e0, dc, mv);
-#pragma unroll
-        for (int j = 0; j < DCM; ++j)
-          if (DC > 0 || j < dc) par ^= Zb[e0 + j];
-        check_core<DC>(mv, dc, ev);
+        const uint32_t sx = check_core<DC, true>(mv, dc, ev);
         lds_row_store<DC>(X + e0, dc, ev);
-        unsat |= par;
+        unsat |= syndrome_bit(sx);
       }
       const unsigned long long b = __ballot(unsat);
       if ((t & 63) == 0) s_unsat[wave] = b != 0ull;
@@ -180,11 +170,8 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
           }
         }
         L[v] = acc;
-        const uint8_t z = acc <= 0.0f ? 1 : 0;
-        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) {
-          X[eid[j]] = clamp_msg(x);
-          Zb[eid[j]] = z;
-        });
+        const bool z = acc <= 0.0f;
+        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = v2c_store(x, z); });
       }
       __syncthreads();  // also orders this iteration's reads of s_unsat before the next writes
       ++it;

@@ -6,33 +6,29 @@
 
 namespace ldpc {
 
-// HBM state of one 64-word tile (FP32 [index][64] unless noted):
-//   M  [nnz]  v->c messages (Eq. 6, clamped)       R [n]  channel LLRs (Eq. 4)
+// HBM state of one 64-word tile (FP32 [index][64]):
+//   M  [nnz]  v->c messages (Eq. 6, clamped), stored with their variable's decision
 //   E0/E1 [nnz] c->v messages of even / odd steps (Eq. 5)
-//   Z  [n] u64 decision masks, bit l = z_v of lane l's word (Eq. 8)
+//   R  [n]  channel LLRs (Eq. 4)
 struct TileState {
   float *E0, *E1, *M, *R;
-  unsigned long long *Z;
 };
 
 // Bytes of one tile's state, each array 256-byte aligned.
 __host__ __device__ inline size_t tile_bytes(int64_t nnz, int32_t n) {
   const size_t e = ((size_t)nnz * TW * sizeof(float) + 255) & ~size_t(255);
   const size_t v = ((size_t)n * TW * sizeof(float) + 255) & ~size_t(255);
-  const size_t z = ((size_t)n * 8 + 255) & ~size_t(255);
-  return 3 * e + v + z;
+  return 3 * e + v;
 }
 
 // Tile state carved from one contiguous per-tile block.
 __device__ __forceinline__ TileState tile_state_block(char *base, int64_t nnz, int32_t n) {
   const size_t e = ((size_t)nnz * TW * sizeof(float) + 255) & ~size_t(255);
-  const size_t v = ((size_t)n * TW * sizeof(float) + 255) & ~size_t(255);
   TileState s;
   s.E0 = (float *)base;
   s.E1 = (float *)(base + e);
   s.M = (float *)(base + 2 * e);
   s.R = (float *)(base + 3 * e);
-  s.Z = (unsigned long long *)(base + 3 * e + v);
   return s;
 }
 
@@ -58,8 +54,8 @@ __device__ __forceinline__ void check_range(const GraphDev &g, int c, int &e0, i
   }
 }
 
-// [B][n] channel LLRs -> R of the tile (through 64 x 64 LDS blocks), the first
-// v->c messages M = clamp(R) on every edge, and the channel decisions Z.
+// [B][n] channel LLRs -> R of the tile (through 64 x 64 LDS blocks) and the first
+// v->c messages M = clamp(R) on every edge, carrying the channel decisions [R <= 0].
 template <int DV>
 __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__restrict__ llr32,
                                             const double *__restrict__ llr64, int cw0, int nvalid, TileState st,
@@ -80,11 +76,9 @@ __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__re
       const int v = v0 + q;
       const float x = stage[lane][q];
       st.R[v * TW + lane] = x;
-      const unsigned long long z = __ballot(x <= 0.0f);
-      if (lane == 0) st.Z[v] = z;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      const float mx = clamp_msg(x);
+      const float mx = v2c_store(x, x <= 0.0f);
       for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
     }
     __syncthreads();
