@@ -36,43 +36,55 @@ if ROOT not in sys.path:
 
 METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batched"
 
-# HBM bytes per launch of the batched kernel on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# runs scaled by a 1 GiB copy (profiles/decode_c2_sweep.md); valid only for the kernel sources they
-# were measured with (sha1 over KERNEL_SOURCES), reported as null otherwise.
-KERNEL_SOURCES = ["paper_2201_04265_amd/csrc/spa_core.h", "paper_2201_04265_amd/csrc/tile.h",
-                  "paper_2201_04265_amd/csrc/multi.hip", "paper_2201_04265_amd/csrc/internal.h"]
-COUNTER_TRAFFIC = {"sources_sha1": "af8949c8bf987d13f8e379c19e1d71d14e46e5d3", "bytes_per_launch": 1676686595905,
-                   "read_bytes": 912527264929, "write_bytes": 764159330976}
+# HBM bytes per launch on the default workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled
+# by a 1 GiB copy (x1.99994 and x1.0; profiles/decode_c2_sweep.md); valid only for the kernel sources
+# they were measured with (sha1 over "sources"), reported as null otherwise.
+_CSRC = "paper_2201_04265_amd/csrc/"
+COUNTER_TRAFFIC = {
+    "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
+               "sha1": "ba38e0087af2e11078ba4865ac854931e1f534f1", "bytes_per_launch": 12100100788, "read_bytes": 5369158132,
+               "write_bytes": 6730942656},
+    "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
+                "sha1": "0f5368ba58054f35c9b49187990e7d7b184699f7", "bytes_per_launch": 1639140048649, "read_bytes": 959011941929,
+                "write_bytes": 680128106720},
+}
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
 # VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 115 VALU instructions per degree-6 check (18 of them quarter-rate exp2 / rcp / log2)
-# and 30 per degree-3 variable; a quarter-rate instruction occupies 4 issue slots.
-STREAM_VALU_SLOTS_PER_EDGE = (115 + 3 * 18) / 6.0 + 30 / 3.0
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-operations per second, 1 slot each
+# code: 99 VALU instructions per degree-6 check (18 of them exp2 / rcp / log2) and 28 per
+# degree-3 variable.  The transcendentals issue at half rate (two slots): the counters show
+# SQ_ACTIVE_INST_VALU x 4 = SQ_INSTS_VALU x 4 + SQ_INSTS_VALU_TRANS_F32 x 4 cycles.
+STREAM_VALU_SLOTS_PER_EDGE = (99 + 18) / 6.0 + 28 / 3.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 
-def counter_traffic():
+def counter_traffic(form, B):
     import hashlib
 
+    c = COUNTER_TRAFFIC.get(form)
+    if c is None or B != 65536:
+        return None
     h = hashlib.sha1()
-    for rel in KERNEL_SOURCES:
+    for rel in c["sources"]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    return COUNTER_TRAFFIC["bytes_per_launch"] if h.hexdigest() == COUNTER_TRAFFIC["sources_sha1"] else None
+    return c["bytes_per_launch"] if h.hexdigest() == c["sha1"] else None
 
 
 def roofline(head, code, B):
     if head["form"] == "stream":
         a = head["achieved_valu_tops"]
         return {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": a / VALU_PEAK_TOPS,
-                "traffic": None, "kernel": head["kernel"], "avg_launch_ms": head["ms_per_step"],
+                "traffic": counter_traffic("stream", B), "kernel": head["kernel"],
+                "avg_launch_ms": head["ms_per_step"],
                 "unit_of_work": "useful edge-iteration x VALU issue slots per edge-iteration (%.2f, compiled "
-                                "code; quarter-rate transcendentals count 4)" % STREAM_VALU_SLOTS_PER_EDGE,
+                                "code; half-rate transcendentals count 2)" % STREAM_VALU_SLOTS_PER_EDGE,
+                "traffic_note": "HBM bytes per launch: LLRs in, posteriors and decisions out (9n per word); "
+                                "messages stay in LDS",
                 "hbm_alg_gb_s_equivalent": head["achieved_gb_s"]}
     return {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
-            "traffic": counter_traffic() if head["form"] == "batched" and B == 65536 else None,
+            "traffic": counter_traffic(head["form"], B),
             "kernel": head["kernel"], "avg_launch_ms": head["ms_per_step"],
             "alg_bytes_per_launch": head["alg_bytes_per_launch"],
             "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
@@ -453,7 +465,7 @@ def main():
         ms = time_launches(torch, lambda: P.decode_stream(g, llr, MAX_ITERS, True, workspace=ws, out=outs),
                            args.steps, args.warmup, stream)
         results["stream"] = summarize(torch, "stream", ms, outs, cw, ebn0s, B, code,
-                                      {"kernel": "stream_decode_kernel<6,3>", "threads": 1024})
+                                      {"kernel": "stream_decode_kernel<6,3>", "threads": 512})
         r = results["stream"]
         r["valu_slots_per_edge_iteration"] = STREAM_VALU_SLOTS_PER_EDGE
         r["achieved_valu_tops"] = r["edge_updates_per_s"] * STREAM_VALU_SLOTS_PER_EDGE / 1e12
