@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ldpc.h"
@@ -19,6 +20,12 @@ struct ldpc_graph_s {
   std::vector<int32_t> row_ptr, col_idx, chk_of_edge, var_ptr, var_edges;
   int device = 0;
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_var_ptr = nullptr, *d_var_edges = nullptr;
+  // Launch facts of the stream form, filled once on its first call (stream.hip).
+  std::mutex stream_mu;
+  bool stream_ready = false;
+  int stream_cus = 0;
+  int stream_lds_limit = 0;                // bytes of LDS one workgroup may use
+  int stream_per_cu[5] = {0, 0, 0, 0, 0};  // resident workgroups per CU with 64 << i threads
 };
 
 // Device view passed to kernels by value.

@@ -218,28 +218,50 @@ StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads) {
 // a single word, and on the n=1032 Table I codes.
 constexpr int kStreamDefaultMaxThreads = 512;
 
-ldpc_status stream_threads(const ldpc_graph_s *g, StreamKernel k, int max_threads, size_t lds, int cus,
-                           int32_t batch, int &best_nt, int &best_per_cu) {
+int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
   const int big = std::max(g->m, g->n);
   const int cap = std::min(max_threads, kStreamDefaultMaxThreads);
   int top = 64;
   while (top < cap && top < big) top *= 2;
-  best_nt = 0;
-  best_per_cu = 0;
+  int best_nt = 0;
   long best = -1;
-  for (int nt = top; nt >= 64; nt /= 2) {
-    int per_cu = 0;
-    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
-    if (per_cu < 1) continue;
-    const long groups = std::min<long>((long)per_cu * cus, batch);
-    const long score = groups * nt;
-    if (score > best) {
-      best = score;
+  for (int i = 4; i >= 0; --i) {
+    const int nt = 64 << i;
+    if (nt > top || g->stream_per_cu[i] < 1) continue;
+    const long groups = std::min<long>((long)g->stream_per_cu[i] * g->stream_cus, batch);
+    if (groups * nt > best) {
+      best = groups * nt;
       best_nt = nt;
-      best_per_cu = per_cu;
     }
   }
-  if (best_nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  return best_nt;
+}
+
+// Device facts the launch needs (the LDS opt-in of the kernel, compute units, resident
+// workgroups per size), queried once per graph instead of on every call.
+ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, size_t lds) {
+  std::lock_guard<std::mutex> lock(g->stream_mu);
+  if (g->stream_ready) return LDPC_OK;
+  int dev = 0, cus = 0, lim = 0;
+  LDPC_HIP_CHECK(hipGetDevice(&dev));
+  LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  LDPC_HIP_CHECK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  g->stream_lds_limit = lim;
+  if (lds + 64 > (size_t)lim) {  // cannot run; remember the limit only
+    g->stream_cus = cus;
+    g->stream_ready = true;
+    return LDPC_OK;
+  }
+  LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (int i = 0; i < 5; ++i) {
+    const int nt = 64 << i;
+    int per_cu = 0;
+    if (nt <= max_threads)
+      LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
+    g->stream_per_cu[i] = per_cu;
+  }
+  g->stream_cus = cus;
+  g->stream_ready = true;
   return LDPC_OK;
 }
 }  // namespace
@@ -270,27 +292,28 @@ extern "C" ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32
   if (!llr || !hard_bits || !posterior || !iters_used || !workspace)
     return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
   if (ws_bytes < 256) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small (256 bytes)");
-  size_t lds = 0;
-  int32_t ok = 0;
-  ldpc_status st = ldpc_stream_lds_bytes(g, &lds, &ok);
-  if (st != LDPC_OK) return st;
-  if (!ok) return set_error(LDPC_ERR_UNSUPPORTED, "word state (" + std::to_string(lds) + " bytes) exceeds LDS");
+  const size_t lds = stream_lds_bytes(g->nnz, g->n);
   int max_threads = 1024;
   StreamKernel k = pick_stream(g, max_threads);
   if (threads > max_threads)
     return set_error(LDPC_ERR_INVALID_ARG,
                      "threads above " + std::to_string(max_threads) + " for this code's check degree");
-  int dev = 0, cus = 0, per_cu = 0, nt = threads;
-  LDPC_HIP_CHECK(hipGetDevice(&dev));
-  LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (nt == 0) {
-    st = stream_threads(g, k, max_threads, lds, cus, batch, nt, per_cu);
-    if (st != LDPC_OK) return st;
+  ldpc_status st = stream_prepare(g, k, max_threads, lds);
+  if (st != LDPC_OK) return st;
+  if (lds + 64 > (size_t)g->stream_lds_limit)
+    return set_error(LDPC_ERR_UNSUPPORTED, "word state (" + std::to_string(lds) + " bytes) exceeds LDS");
+  const int nt = threads ? threads : stream_threads(g, max_threads, batch);
+  if (nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  int per_cu = 0;
+  if ((nt & (nt - 1)) == 0) {  // powers of two: resident counts known
+    int lg = 0;
+    while ((64 << lg) < nt) ++lg;
+    per_cu = g->stream_per_cu[lg];
   } else {
     LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
-    if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
   }
+  const int cus = g->stream_cus;
+  if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
   const int grid = std::min(batch, cus * per_cu);
   int *counter = (int *)workspace;
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, counter);

@@ -51,7 +51,7 @@ def test_c2_equals_plain(P, ebn0, key):
     same(a, b)
 
 
-@pytest.mark.parametrize("threads", [64, 256, 1024])
+@pytest.mark.parametrize("threads", [64, 192, 256, 1024])
 def test_workgroup_sizes_agree(P, threads):
     code = W.code("c5")
     g = P.Graph.from_code(code)
