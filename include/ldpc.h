@@ -205,7 +205,10 @@ ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, cons
  *   L_v = R_v + sum_{e in N(v)} w[T-1][e] E^(T)_e.
  * All weights 1 gives ldpc_decode(early_stop = 0, max_iters = T) bit for bit.
  * Sizes: checkpoints (the A^(t) of every iteration, kept between forward and
- * backward), forward and backward workspaces, all device bytes.
+ * backward), forward and backward workspaces, all device bytes, for this graph,
+ * batch and T.  Their layout is internal: a code whose per-word backward state
+ * (4 x edges + 4 x n bytes) fits the LDS of one workgroup runs one word per
+ * workgroup with its messages on chip; larger codes run 64-word tiles in HBM.
  */
 ldpc_status ldpc_unrolled_sizes(ldpc_graph_t g, int32_t batch, int32_t T, size_t *ckpt_bytes, size_t *fwd_ws_bytes,
                                 size_t *bwd_ws_bytes);

@@ -26,6 +26,7 @@ struct ldpc_graph_s {
   int stream_cus = 0;
   int stream_lds_limit = 0;                // bytes of LDS one workgroup may use
   int stream_per_cu[5] = {0, 0, 0, 0, 0};  // resident workgroups per CU with 64 << i threads
+  int lds_limit = 0;                       // LDS bytes per workgroup (unrolled form), 0 = not queried
 };
 
 // Device view passed to kernels by value.

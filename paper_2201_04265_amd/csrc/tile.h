@@ -119,4 +119,50 @@ __device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int
 }
 
 
+// A check's messages are contiguous (edge e0 = c * DC for a fixed degree), so a row is
+// moved with 16- or 8-byte LDS accesses when DC allows: a check's row then starts on
+// a multiple of its access width, and consecutive threads' rows fall on disjoint banks.
+template <int DC>
+__device__ __forceinline__ void lds_row_load(const float *row, int dc, float *v) {
+  if constexpr (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 4; ++h) {
+      const float4 x = reinterpret_cast<const float4 *>(row)[h];
+      v[4 * h] = x.x;
+      v[4 * h + 1] = x.y;
+      v[4 * h + 2] = x.z;
+      v[4 * h + 3] = x.w;
+    }
+  } else if constexpr (DC > 0 && DC % 2 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 2; ++h) {
+      const float2 x = reinterpret_cast<const float2 *>(row)[h];
+      v[2 * h] = x.x;
+      v[2 * h + 1] = x.y;
+    }
+  } else {
+    constexpr int DM = DC > 0 ? DC : -DC;
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+      if (DC > 0 || j < dc) v[j] = row[j];
+  }
+}
+
+template <int DC>
+__device__ __forceinline__ void lds_row_store(float *row, int dc, const float *v) {
+  if constexpr (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 4; ++h)
+      reinterpret_cast<float4 *>(row)[h] = make_float4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+  } else if constexpr (DC > 0 && DC % 2 == 0) {
+#pragma unroll
+    for (int h = 0; h < DC / 2; ++h) reinterpret_cast<float2 *>(row)[h] = make_float2(v[2 * h], v[2 * h + 1]);
+  } else {
+    constexpr int DM = DC > 0 ? DC : -DC;
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+      if (DC > 0 || j < dc) row[j] = v[j];
+  }
+}
+
 }  // namespace ldpc

@@ -47,6 +47,38 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
+// Adjoint of the check rule for one check, given a_i = dE_i cosh^2(E_i/2) and
+// tau_u = tanh(M_u/2): emits dA_j = [-20 <= A_j <= 20] sech^2(M_j/2) sum_{i != j} a_i
+// prod_{u != i, j} tau_u, with the inner sum from prefix and suffix pairs (P, S).
+template <int DC, typename Emit>
+__device__ __forceinline__ void check_adjoint(const float *av, const float *mv, const float *tau, const float *a, int dc,
+                                              Emit &&emit) {
+  constexpr int DCM = DC > 0 ? DC : -DC;
+  float pP[DCM], pS[DCM];
+  float P = 1.0f, S = 0.0f;
+#pragma unroll
+  for (int j = 0; j < DCM; ++j) {
+    if (DC > 0 || j < dc) {
+      pP[j] = P;
+      pS[j] = S;
+      S = S * tau[j] + a[j] * P;
+      P = P * tau[j];
+    }
+  }
+  P = 1.0f;
+  S = 0.0f;
+#pragma unroll
+  for (int j = DCM - 1; j >= 0; --j) {
+    if (DC > 0 || j < dc) {
+      const float sx = pS[j] * P + S * pP[j];
+      const float dm = sech2_half(mv[j]) * sx;
+      emit(j, (av[j] >= -kLmax && av[j] <= kLmax) ? dm : 0.0f);
+      S = S * tau[j] + a[j] * P;
+      P = P * tau[j];
+    }
+  }
+}
+
 struct UnrolledTile {
   float *A;  // [T][nnz][64] checkpoints of the v->c messages, pre-clamp
   float *E;  // [nnz][64] c->v messages of the current iteration (forward)
@@ -220,31 +252,7 @@ __global__ void __launch_bounds__(512)
           tau[j] = tanhf(0.5f * mv[j]);
         }
       }
-      // prefix pairs over items < j, then suffix pairs over items > j
-      float pP[DCM], pS[DCM];
-      float P = 1.0f, S = 0.0f;
-#pragma unroll
-      for (int j = 0; j < DCM; ++j) {
-        if (DC > 0 || j < dc) {
-          pP[j] = P;
-          pS[j] = S;
-          S = S * tau[j] + a[j] * P;
-          P = P * tau[j];
-        }
-      }
-      P = 1.0f;
-      S = 0.0f;
-#pragma unroll
-      for (int j = DCM - 1; j >= 0; --j) {
-        if (DC > 0 || j < dc) {
-          const float sx = pS[j] * P + S * pP[j];
-          const float dm = sech2_half(mv[j]) * sx;
-          const float da = (av[j] >= -kLmax && av[j] <= kLmax) ? dm : 0.0f;
-          st.D[(e0 + j) * TW + lane] = da;
-          S = S * tau[j] + a[j] * P;
-          P = P * tau[j];
-        }
-      }
+      check_adjoint<DC>(av, mv, tau, a, dc, [&](int j, float da) { st.D[(e0 + j) * TW + lane] = da; });
     }
     __syncthreads();
     for (int v = wave; v < g.n; v += W) {
@@ -284,6 +292,189 @@ __global__ void __launch_bounds__(512)
   tile_to_rows(st.R, g.n, cw0, nvalid, grad_llr, stage, wave, W, lane);
 }
 
+// ---- LDS form: one word per workgroup -------------------------------------------
+//
+// For codes whose per-word state fits in LDS the same iterations run with the word's
+// messages on chip, one word per workgroup (threads take checks, then variables, in
+// Algorithm 1's interleave), so HBM carries only the LLRs, the weights, the outputs and
+// the checkpoints.  Same operations in the same order per word as the tile kernels:
+// the forward's outputs are identical to theirs (and, with all weights 1, to the plain
+// decoder's).  Checkpoints are [word][t][E] (A^(t)), written by the check phase that
+// reads them.  In the backward each workgroup takes K consecutive words and adds their
+// weight gradients, in word order, into its own [T][E] row of the workspace; the rows
+// are then summed in order (reduce_tiles): deterministic, K fixed by the batch size.
+
+__host__ __device__ inline size_t unrolled_lds_bwd_bytes(int64_t nnz, int32_t n) {
+  return (size_t)nnz * 4 + (size_t)n * 4 + 16;
+}
+__host__ __device__ inline size_t unrolled_lds_fwd_bytes(int64_t nnz) { return (size_t)nnz * 4 + 16; }
+// Words per backward workgroup: a function of the batch only, so that the summation
+// order of the weight gradients does not depend on the device.
+__host__ __device__ inline int unrolled_lds_words_per_group(int32_t batch) {
+  return batch <= 2048 ? 1 : (batch + 2047) / 2048;
+}
+
+template <int DC, int DV>
+__global__ void __launch_bounds__(512)
+    unrolled_fwd_lds(GraphDev g, const float *__restrict__ llr, const float *__restrict__ w, int B, int T,
+                     float *__restrict__ ckpt, float *__restrict__ post) {
+  constexpr int DVM = DV > 0 ? DV : -DV;
+  constexpr int DCM = DC > 0 ? DC : -DC;
+  extern __shared__ __align__(16) float smem[];
+  float *X = smem;  // A^(t) before the check phase, E^(t) after it
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int word = blockIdx.x;
+  const size_t n = (size_t)g.n, E = (size_t)g.nnz;
+  const float *R = llr + (size_t)word * n;
+  float *out = post + (size_t)word * n;
+  for (int v = tid; v < g.n; v += NT) {  // A^(1) = R on every edge
+    int p0, dv;
+    var_range<DV>(g, v, p0, dv);
+    const float r = R[v];
+    for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = r;
+    if (T == 0) out[v] = r;
+  }
+  __syncthreads();
+  for (int t = 1; t <= T; ++t) {
+    float *Ck = ckpt + ((size_t)word * T + (t - 1)) * E;
+    for (int c = tid; c < g.m; c += NT) {
+      int e0, dc;
+      check_range<DC>(g, c, e0, dc);
+      float av[DCM], mv[DCM], ev[DCM];
+      lds_row_load<DC>(X + e0, dc, av);
+#pragma unroll
+      for (int j = 0; j < DCM; ++j) {
+        if (DC > 0 || j < dc) {
+          Ck[e0 + j] = av[j];
+          mv[j] = clamp_msg(av[j]);
+        }
+      }
+      check_core<DC>(mv, dc, ev);
+      lds_row_store<DC>(X + e0, dc, ev);
+    }
+    __syncthreads();
+    const float *wt = w + (size_t)(t - 1) * E;
+    for (int v = tid; v < g.n; v += NT) {
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      float ev[DVM], pre[DVM];
+      int eid[DVM];
+#pragma unroll
+      for (int j = 0; j < DVM; ++j) {
+        if (DV > 0 || j < dv) {
+          eid[j] = g.var_edges[p0 + j];
+          ev[j] = wt[eid[j]] * X[eid[j]];
+        }
+      }
+      float acc = R[v];
+#pragma unroll
+      for (int j = 0; j < DVM; ++j) {
+        if (DV > 0 || j < dv) {
+          pre[j] = acc;
+          acc += ev[j];
+        }
+      }
+      if (t < T)
+        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = x; });
+      else
+        out[v] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <int DC, int DV>
+__global__ void __launch_bounds__(512)
+    unrolled_bwd_lds(GraphDev g, const float *__restrict__ w, int B, int T, int K, const float *__restrict__ ckpt,
+                     const float *__restrict__ gpost, float *__restrict__ wpart, float *__restrict__ grad_llr) {
+  constexpr int DVM = DV > 0 ? DV : -DV;
+  constexpr int DCM = DC > 0 ? DC : -DC;
+  extern __shared__ __align__(16) float smem[];
+  float *X = smem;        // G^(t) before the check phase, dA^(t) after it
+  float *dR = X + g.nnz;  // d loss / d R of the word
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const size_t n = (size_t)g.n, E = (size_t)g.nnz;
+  float *wp = wpart + (size_t)blockIdx.x * (size_t)T * E;
+  for (int k = 0; k < K; ++k) {
+    const int word = blockIdx.x * K + k;
+    if (word >= B) break;  // same in every thread
+    const float *gL = gpost + (size_t)word * n;
+    for (int v = tid; v < g.n; v += NT) {  // G^(T) = gL on every edge of v, dR = gL
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      const float gl = gL[v];
+      dR[v] = gl;
+      for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = gl;
+    }
+    __syncthreads();
+    for (int t = T; t >= 1; --t) {
+      const float *Ck = ckpt + ((size_t)word * T + (t - 1)) * E;
+      const float *wt = w + (size_t)(t - 1) * E;
+      float *wpt = wp + (size_t)(t - 1) * E;
+      for (int c = tid; c < g.m; c += NT) {
+        int e0, dc;
+        check_range<DC>(g, c, e0, dc);
+        float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], gg[DCM];
+#pragma unroll
+        for (int j = 0; j < DCM; ++j) {
+          if (DC > 0 || j < dc) {
+            av[j] = Ck[e0 + j];
+            mv[j] = clamp_msg(av[j]);
+          }
+        }
+        check_core<DC>(mv, dc, ev);  // E^(t), recomputed exactly as in the forward
+        lds_row_load<DC>(X + e0, dc, gg);
+#pragma unroll
+        for (int j = 0; j < DCM; ++j) {
+          if (DC > 0 || j < dc) {
+            const float contrib = gg[j] * ev[j];
+            wpt[e0 + j] = k == 0 ? contrib : wpt[e0 + j] + contrib;
+            a[j] = gg[j] * wt[e0 + j] * cosh2_half(ev[j]);
+            tau[j] = tanhf(0.5f * mv[j]);
+          }
+        }
+        check_adjoint<DC>(av, mv, tau, a, dc, [&](int j, float da) { X[e0 + j] = da; });
+      }
+      __syncthreads();
+      for (int v = tid; v < g.n; v += NT) {
+        int p0, dv;
+        var_range<DV>(g, v, p0, dv);
+        float dv_[DVM], pre[DVM];
+        int eid[DVM];
+#pragma unroll
+        for (int j = 0; j < DVM; ++j) {
+          if (DV > 0 || j < dv) {
+            eid[j] = g.var_edges[p0 + j];
+            dv_[j] = X[eid[j]];
+          }
+        }
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < DVM; ++j) {
+          if (DV > 0 || j < dv) {
+            pre[j] = acc;
+            acc += dv_[j];
+          }
+        }
+        dR[v] += acc;
+        if (t > 1) {
+          float suf = 0.0f;
+#pragma unroll
+          for (int j = DVM - 1; j >= 0; --j) {
+            if (DV > 0 || j < dv) {
+              X[eid[j]] = pre[j] + suf;
+              suf += dv_[j];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int v = tid; v < g.n; v += NT) grad_llr[(size_t)word * n + v] = dR[v];
+    __syncthreads();  // dR and X are reused by the next word
+  }
+}
+
 // grad_w[i] = sum over tiles (ascending) of the per-tile partials.
 __global__ void reduce_tiles(const float *__restrict__ wpart, int tiles, size_t len, float *__restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,10 +488,44 @@ __global__ void reduce_tiles(const float *__restrict__ wpart, int tiles, size_t 
 
 using namespace ldpc;
 
+namespace {
+
+// Largest dynamic LDS one workgroup of the graph's device may use (queried once).
+int lds_limit(ldpc_graph_s *g) {
+  std::lock_guard<std::mutex> lock(g->stream_mu);
+  if (g->lds_limit == 0) {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      g->lds_limit = lim;
+  }
+  return g->lds_limit;
+}
+
+// The LDS form runs when a word's backward state (4E + 4n bytes) fits one workgroup.
+bool use_lds_form(ldpc_graph_s *g) { return unrolled_lds_bwd_bytes(g->nnz, g->n) + 64 <= (size_t)lds_limit(g); }
+
+int lds_form_threads(const ldpc_graph_s *g) {
+  const int big = std::max(g->m, g->n);
+  int nt = 64;
+  while (nt < 512 && nt < big) nt *= 2;
+  return nt;
+}
+
+}  // namespace
+
 extern "C" ldpc_status ldpc_unrolled_sizes(ldpc_graph_t g, int32_t batch, int32_t T, size_t *ckpt_bytes,
                                            size_t *fwd_ws_bytes, size_t *bwd_ws_bytes) {
   if (!g) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
   if (batch < 0 || T < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative batch or T");
+  if (use_lds_form(g)) {
+    const size_t groups = ((size_t)batch + unrolled_lds_words_per_group(batch) - 1) /
+                          (size_t)unrolled_lds_words_per_group(batch);
+    if (ckpt_bytes) *ckpt_bytes = al256((size_t)batch * (size_t)T * (size_t)g->nnz * 4);
+    if (fwd_ws_bytes) *fwd_ws_bytes = 256;
+    if (bwd_ws_bytes) *bwd_ws_bytes = al256(groups * (size_t)T * (size_t)g->nnz * 4) + 256;
+    return LDPC_OK;
+  }
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
   if (ckpt_bytes) *ckpt_bytes = tiles * unrolled_ckpt_tile(g->nnz, T);
   if (fwd_ws_bytes) *fwd_ws_bytes = tiles * unrolled_ws_tile(g->nnz, g->n);
@@ -313,6 +538,8 @@ namespace {
 using FwdKernel = void (*)(GraphDev, const float *, const float *, int, int, char *, char *, float *);
 using BwdKernel = void (*)(GraphDev, const float *, int, int, const char *, const float *, char *, float *,
                            float *);
+using LdsFwdKernel = void (*)(GraphDev, const float *, const float *, int, int, float *, float *);
+using LdsBwdKernel = void (*)(GraphDev, const float *, int, int, int, const float *, const float *, float *, float *);
 
 ldpc_status check_buffers(int32_t batch, int32_t T, const void *in, const void *out, const void *w, const void *ws,
                           size_t ws_bytes, size_t need_ws, const void *ck, size_t ck_bytes, size_t need_ck) {
@@ -335,6 +562,19 @@ extern "C" ldpc_status ldpc_unrolled_forward(ldpc_graph_t g, const float *llr, c
   if (st != LDPC_OK) return st;
   st = check_buffers(batch, T, llr, posterior, w, workspace, ws_bytes, fw, ckpt, ckpt_bytes, ck);
   if (st != LDPC_OK || batch == 0) return st;
+  if (use_lds_form(g)) {
+    LdsFwdKernel kl = nullptr;
+#define LDPC_PICK(C, V) kl = unrolled_fwd_lds<C, V>
+    LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
+#undef LDPC_PICK
+    const size_t lds = unrolled_lds_fwd_bytes(g->nnz);
+    if (lds > 65536)
+      LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kl, dim3((unsigned)batch), dim3(lds_form_threads(g)), lds, stream, graph_dev(g), llr, w,
+                       (int)batch, (int)T, (float *)ckpt, posterior);
+    LDPC_HIP_CHECK(hipGetLastError());
+    return LDPC_OK;
+  }
   FwdKernel k = nullptr;
 #define LDPC_PICK(C, V) k = unrolled_fwd_kernel<C, V>
   LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
@@ -364,6 +604,28 @@ extern "C" ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, co
   }
   st = check_buffers(batch, T, grad_post, grad_llr, w, workspace, ws_bytes, bw, ckpt, ckpt_bytes, ck);
   if (st != LDPC_OK) return st;
+  if (use_lds_form(g)) {
+    LdsBwdKernel kl = nullptr;
+#define LDPC_PICK(C, V) kl = unrolled_bwd_lds<C, V>
+    LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
+#undef LDPC_PICK
+    const size_t lds = unrolled_lds_bwd_bytes(g->nnz, g->n);
+    if (lds > 65536)
+      LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int K = unrolled_lds_words_per_group(batch);
+    const int groups = (batch + K - 1) / K;
+    float *wpart = (float *)workspace;
+    hipLaunchKernelGGL(kl, dim3((unsigned)groups), dim3(lds_form_threads(g)), lds, stream, graph_dev(g), w,
+                       (int)batch, (int)T, K, (const float *)ckpt, grad_post, wpart, grad_llr);
+    LDPC_HIP_CHECK(hipGetLastError());
+    if (T > 0) {
+      const size_t len = (size_t)T * (size_t)g->nnz;
+      hipLaunchKernelGGL(reduce_tiles, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, stream, wpart, groups, len,
+                         grad_w);
+      LDPC_HIP_CHECK(hipGetLastError());
+    }
+    return LDPC_OK;
+  }
   BwdKernel k = nullptr;
 #define LDPC_PICK(C, V) k = unrolled_bwd_kernel<C, V>
   LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
