@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(512)
 // decoder's).  Checkpoints are [word][t][E] (A^(t)), written by the check phase that
 // reads them.  In the backward each workgroup takes K consecutive words and adds their
 // weight gradients, in word order, into its own [T][E] row of the workspace; the rows
-// are then summed in order (reduce_tiles): deterministic, K fixed by the batch size.
+// are then summed in a fixed order (reduce_rows): deterministic, K fixed by the batch size.
 
 __host__ __device__ inline size_t unrolled_lds_bwd_bytes(int64_t nnz, int32_t n) {
   return (size_t)nnz * 4 + (size_t)n * 4 + 16;
@@ -475,13 +475,39 @@ __global__ void __launch_bounds__(512)
   }
 }
 
-// grad_w[i] = sum over tiles (ascending) of the per-tile partials.
-__global__ void reduce_tiles(const float *__restrict__ wpart, int tiles, size_t len, float *__restrict__ out) {
+// grad_w[i] = sum of the rows' partials wpart[r][i] in a fixed order: rows are summed in
+// ascending order within chunks of kReduceChunk, then the chunk sums in ascending order
+// (one pass when there is a single chunk).  Deterministic for a given row count.
+constexpr int kReduceChunk = 32;
+
+__global__ void reduce_rows_chunks(const float *__restrict__ wpart, int rows, size_t len, float *__restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
+  const int r0 = blockIdx.y * kReduceChunk, r1 = min(rows, r0 + kReduceChunk);
   float s = 0.0f;
-  for (int k = 0; k < tiles; ++k) s += wpart[(size_t)k * len + i];
-  out[i] = s;
+  for (int r = r0; r < r1; ++r) s += wpart[(size_t)r * len + i];
+  out[(size_t)blockIdx.y * len + i] = s;
+}
+
+inline size_t reduce_part_bytes(int rows, size_t len) {
+  const size_t chunks = ((size_t)rows + kReduceChunk - 1) / kReduceChunk;
+  return chunks > 1 ? chunks * len * sizeof(float) : 0;
+}
+
+// part: reduce_part_bytes(rows, len) bytes of scratch.  rows == 0 writes zeros.
+ldpc_status reduce_rows(const float *wpart, int rows, size_t len, float *part, float *out, hipStream_t stream) {
+  const unsigned cols = (unsigned)((len + 255) / 256);
+  const int chunks = (rows + kReduceChunk - 1) / kReduceChunk;
+  if (chunks <= 1) {
+    hipLaunchKernelGGL(reduce_rows_chunks, dim3(cols, 1), dim3(256), 0, stream, wpart, rows, len, out);
+    LDPC_HIP_CHECK(hipGetLastError());
+    return LDPC_OK;
+  }
+  hipLaunchKernelGGL(reduce_rows_chunks, dim3(cols, (unsigned)chunks), dim3(256), 0, stream, wpart, rows, len, part);
+  LDPC_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(reduce_rows_chunks, dim3(cols, 1), dim3(256), 0, stream, (const float *)part, chunks, len, out);
+  LDPC_HIP_CHECK(hipGetLastError());
+  return LDPC_OK;
 }
 
 }  // namespace ldpc
@@ -521,16 +547,19 @@ extern "C" ldpc_status ldpc_unrolled_sizes(ldpc_graph_t g, int32_t batch, int32_
   if (use_lds_form(g)) {
     const size_t groups = ((size_t)batch + unrolled_lds_words_per_group(batch) - 1) /
                           (size_t)unrolled_lds_words_per_group(batch);
-    if (ckpt_bytes) *ckpt_bytes = al256((size_t)batch * (size_t)T * (size_t)g->nnz * 4);
+    const size_t len = (size_t)T * (size_t)g->nnz;
+    if (ckpt_bytes) *ckpt_bytes = al256((size_t)batch * len * 4);
     if (fwd_ws_bytes) *fwd_ws_bytes = 256;
-    if (bwd_ws_bytes) *bwd_ws_bytes = al256(groups * (size_t)T * (size_t)g->nnz * 4) + 256;
+    if (bwd_ws_bytes) *bwd_ws_bytes = al256(groups * len * 4) + al256(reduce_part_bytes((int)groups, len)) + 256;
     return LDPC_OK;
   }
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
+  const size_t len = (size_t)T * (size_t)g->nnz;
   if (ckpt_bytes) *ckpt_bytes = tiles * unrolled_ckpt_tile(g->nnz, T);
   if (fwd_ws_bytes) *fwd_ws_bytes = tiles * unrolled_ws_tile(g->nnz, g->n);
   if (bwd_ws_bytes)
-    *bwd_ws_bytes = tiles * unrolled_ws_tile(g->nnz, g->n) + al256(tiles * (size_t)T * (size_t)g->nnz * 4);
+    *bwd_ws_bytes = tiles * unrolled_ws_tile(g->nnz, g->n) + al256(tiles * len * 4) +
+                    al256(reduce_part_bytes((int)tiles, len));
   return LDPC_OK;
 }
 
@@ -594,12 +623,7 @@ extern "C" ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, co
   if (st != LDPC_OK) return st;
   if (T > 0 && !grad_w) return set_error(LDPC_ERR_INVALID_ARG, "grad_w is NULL");
   if (batch == 0) {
-    if (T > 0) {
-      const size_t len = (size_t)T * (size_t)g->nnz;
-      hipLaunchKernelGGL(reduce_tiles, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, stream, nullptr, 0, len,
-                         grad_w);
-      LDPC_HIP_CHECK(hipGetLastError());
-    }
+    if (T > 0) return reduce_rows(nullptr, 0, (size_t)T * (size_t)g->nnz, nullptr, grad_w, stream);
     return LDPC_OK;
   }
   st = check_buffers(batch, T, grad_post, grad_llr, w, workspace, ws_bytes, bw, ckpt, ckpt_bytes, ck);
@@ -614,16 +638,13 @@ extern "C" ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, co
       LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int K = unrolled_lds_words_per_group(batch);
     const int groups = (batch + K - 1) / K;
+    const size_t len = (size_t)T * (size_t)g->nnz;
     float *wpart = (float *)workspace;
+    float *part = (float *)((char *)workspace + al256((size_t)groups * len * 4));
     hipLaunchKernelGGL(kl, dim3((unsigned)groups), dim3(lds_form_threads(g)), lds, stream, graph_dev(g), w,
                        (int)batch, (int)T, K, (const float *)ckpt, grad_post, wpart, grad_llr);
     LDPC_HIP_CHECK(hipGetLastError());
-    if (T > 0) {
-      const size_t len = (size_t)T * (size_t)g->nnz;
-      hipLaunchKernelGGL(reduce_tiles, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, stream, wpart, groups, len,
-                         grad_w);
-      LDPC_HIP_CHECK(hipGetLastError());
-    }
+    if (T > 0) return reduce_rows(wpart, groups, len, part, grad_w, stream);
     return LDPC_OK;
   }
   BwdKernel k = nullptr;
@@ -638,9 +659,8 @@ extern "C" ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, co
   LDPC_HIP_CHECK(hipGetLastError());
   if (T > 0) {
     const size_t len = (size_t)T * (size_t)g->nnz;
-    hipLaunchKernelGGL(reduce_tiles, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, stream, wpart, tiles, len,
-                       grad_w);
-    LDPC_HIP_CHECK(hipGetLastError());
+    float *part = (float *)((char *)wpart + al256((size_t)tiles * len * 4));
+    return reduce_rows(wpart, tiles, len, part, grad_w, stream);
   }
   return LDPC_OK;
 }
