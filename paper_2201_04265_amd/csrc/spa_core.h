@@ -64,8 +64,11 @@ __device__ __forceinline__ float v2c_store(float x, bool z) {
 // patterns: bit 31 is the sign of the product of all messages, and for stored
 // messages bit 30 is the parity of the decisions they carry (syndrome_bit).
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
-template <int DC, bool STORED = false>
-__device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *eout) {
+// AUX: also returns, per edge, q_j = e^-|M_j| in aq and r_j = e^|E_j| (the ratio s / d
+// whose logarithm is the output magnitude) in ar, for the adjoint.
+template <int DC, bool STORED = false, bool AUX = false>
+__device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *eout, float *aq = nullptr,
+                                               float *ar = nullptr) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   // qs[j] = q_j with M_j's sign bit, so that the messages themselves are not kept
@@ -123,7 +126,12 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
         os = fmaf(pd[j], d, ps[j] * s);
       }
       // |log2|: rounding can put os / od a hair below 1 when the exact output is ~1e-7
-      const float mag = fabsf(__builtin_amdgcn_logf(os * __builtin_amdgcn_rcpf(od))) * kLn2;
+      const float ratio = os * __builtin_amdgcn_rcpf(od);
+      const float mag = fabsf(__builtin_amdgcn_logf(ratio)) * kLn2;
+      if (AUX) {
+        aq[j] = fabsf(qs[j]);
+        ar[j] = fmaxf(ratio, 1.0f);
+      }
       const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
       eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
       const float q = fabsf(qs[j]);

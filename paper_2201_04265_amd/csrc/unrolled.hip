@@ -27,17 +27,25 @@
 
 namespace ldpc {
 
-// sech^2(x/2) = 4q / (1+q)^2 and cosh^2(x/2) = (1+q)^2 / (4q) with q = e^-|x|
-// (no 1 - tanh^2 cancellation).
-__device__ __forceinline__ float sech2_half(float x) {
-  const float q = expf(-fabsf(x));
-  const float d = 1.0f + q;
-  return 4.0f * q / (d * d);
-}
-__device__ __forceinline__ float cosh2_half(float x) {
-  const float q = expf(-fabsf(x));
-  const float d = 1.0f + q;
-  return d * d / (4.0f * q);
+// Factors of the check rule's derivative for one edge, from what the check rule
+// computed anyway: q = e^-|m| of the incoming message m and r = e^|E| of the outgoing E.
+//   tau   = tanh(m/2)    = sign(m) (1 - q) / (1 + q), with 1 - q = 1 - e^-x from its
+//                          Taylor series x (1 - x/2 + x^2/6 - x^3/24 + x^4/120) when
+//                          x = |m| < 0.15 (no cancellation)
+//   sech2 = sech^2(m/2)  = 4 q / (1 + q)^2          (no 1 - tanh^2 cancellation)
+//   cosh2 = cosh^2(E/2)  = (r + 1)^2 / (4 r)
+__device__ __forceinline__ void adjoint_factors(float m, float q, float r, float &tau, float &sech2, float &cosh2) {
+  const float x = fabsf(m);
+  float t = fmaf(x, 1.0f / 120.0f, -1.0f / 24.0f);
+  t = fmaf(x, t, 1.0f / 6.0f);
+  t = fmaf(x, t, -0.5f);
+  t = fmaf(x, t, 1.0f);
+  const float u = x < 0.15f ? x * t : 1.0f - q;
+  const float ip = __builtin_amdgcn_rcpf(1.0f + q);
+  tau = copysignf(u * ip, m);
+  sech2 = 4.0f * q * ip * ip;
+  const float rp = r + 1.0f;
+  cosh2 = 0.25f * rp * rp * __builtin_amdgcn_rcpf(r);
 }
 
 // Sum over the 64 lanes in a fixed butterfly order (same result in every lane).
@@ -47,12 +55,13 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-// Adjoint of the check rule for one check, given a_i = dE_i cosh^2(E_i/2) and
-// tau_u = tanh(M_u/2): emits dA_j = [-20 <= A_j <= 20] sech^2(M_j/2) sum_{i != j} a_i
-// prod_{u != i, j} tau_u, with the inner sum from prefix and suffix pairs (P, S).
+// Adjoint of the check rule for one check, given a_i = dE_i cosh^2(E_i/2),
+// tau_u = tanh(M_u/2) and sech2_j = sech^2(M_j/2): emits dA_j = [-20 <= A_j <= 20]
+// sech2_j sum_{i != j} a_i prod_{u != i, j} tau_u, with the inner sum from prefix and
+// suffix pairs (P, S).
 template <int DC, typename Emit>
-__device__ __forceinline__ void check_adjoint(const float *av, const float *mv, const float *tau, const float *a, int dc,
-                                              Emit &&emit) {
+__device__ __forceinline__ void check_adjoint(const float *av, const float *sech2, const float *tau, const float *a,
+                                              int dc, Emit &&emit) {
   constexpr int DCM = DC > 0 ? DC : -DC;
   float pP[DCM], pS[DCM];
   float P = 1.0f, S = 0.0f;
@@ -71,7 +80,7 @@ __device__ __forceinline__ void check_adjoint(const float *av, const float *mv, 
   for (int j = DCM - 1; j >= 0; --j) {
     if (DC > 0 || j < dc) {
       const float sx = pS[j] * P + S * pP[j];
-      const float dm = sech2_half(mv[j]) * sx;
+      const float dm = sech2[j] * sx;
       emit(j, (av[j] >= -kLmax && av[j] <= kLmax) ? dm : 0.0f);
       S = S * tau[j] + a[j] * P;
       P = P * tau[j];
@@ -233,7 +242,7 @@ __global__ void __launch_bounds__(512)
     for (int c = wave; c < g.m; c += W) {
       int e0, dc;
       check_range<DC>(g, c, e0, dc);
-      float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM];
+      float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], sh[DCM], qv[DCM], rv[DCM];
 #pragma unroll
       for (int j = 0; j < DCM; ++j) {
         if (DC > 0 || j < dc) {
@@ -241,18 +250,19 @@ __global__ void __launch_bounds__(512)
           mv[j] = clamp_msg(av[j]);
         }
       }
-      check_core<DC>(mv, dc, ev);  // E^(t), recomputed exactly as in the forward
+      check_core<DC, false, true>(mv, dc, ev, qv, rv);  // E^(t), recomputed exactly as in the forward
 #pragma unroll
       for (int j = 0; j < DCM; ++j) {
         if (DC > 0 || j < dc) {
           const float gg = st.G[(e0 + j) * TW + lane];
           const float s = wave_sum(gg * ev[j]);
           if (lane == 0) wpt[e0 + j] = s;
-          a[j] = gg * wt[e0 + j] * cosh2_half(ev[j]);
-          tau[j] = tanhf(0.5f * mv[j]);
+          float ch;
+          adjoint_factors(mv[j], qv[j], rv[j], tau[j], sh[j], ch);
+          a[j] = gg * wt[e0 + j] * ch;
         }
       }
-      check_adjoint<DC>(av, mv, tau, a, dc, [&](int j, float da) { st.D[(e0 + j) * TW + lane] = da; });
+      check_adjoint<DC>(av, sh, tau, a, dc, [&](int j, float da) { st.D[(e0 + j) * TW + lane] = da; });
     }
     __syncthreads();
     for (int v = wave; v < g.n; v += W) {
@@ -414,7 +424,7 @@ __global__ void __launch_bounds__(512)
       for (int c = tid; c < g.m; c += NT) {
         int e0, dc;
         check_range<DC>(g, c, e0, dc);
-        float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], gg[DCM];
+        float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], gg[DCM], sh[DCM], qv[DCM], rv[DCM];
 #pragma unroll
         for (int j = 0; j < DCM; ++j) {
           if (DC > 0 || j < dc) {
@@ -422,18 +432,19 @@ __global__ void __launch_bounds__(512)
             mv[j] = clamp_msg(av[j]);
           }
         }
-        check_core<DC>(mv, dc, ev);  // E^(t), recomputed exactly as in the forward
+        check_core<DC, false, true>(mv, dc, ev, qv, rv);  // E^(t), recomputed exactly as in the forward
         lds_row_load<DC>(X + e0, dc, gg);
 #pragma unroll
         for (int j = 0; j < DCM; ++j) {
           if (DC > 0 || j < dc) {
             const float contrib = gg[j] * ev[j];
             wpt[e0 + j] = k == 0 ? contrib : wpt[e0 + j] + contrib;
-            a[j] = gg[j] * wt[e0 + j] * cosh2_half(ev[j]);
-            tau[j] = tanhf(0.5f * mv[j]);
+            float ch;
+            adjoint_factors(mv[j], qv[j], rv[j], tau[j], sh[j], ch);
+            a[j] = gg[j] * wt[e0 + j] * ch;
           }
         }
-        check_adjoint<DC>(av, mv, tau, a, dc, [&](int j, float da) { X[e0 + j] = da; });
+        check_adjoint<DC>(av, sh, tau, a, dc, [&](int j, float da) { X[e0 + j] = da; });
       }
       __syncthreads();
       for (int v = tid; v < g.n; v += NT) {
