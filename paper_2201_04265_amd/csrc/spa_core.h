@@ -16,6 +16,15 @@ constexpr int TW = 64;          // words per tile (lanes per wavefront)
 constexpr float kLmax = 20.0f;  // saturation of variable-to-check messages
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Workgroup barrier that orders LDS only: global loads and stores in flight are not
+// waited for.  For kernels whose threads exchange data only through LDS (what they
+// write to global memory is read by later launches or by the writing thread itself).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 constexpr float kL2e = 1.44269504088896341f;  // log2(e) = 1 / ln 2

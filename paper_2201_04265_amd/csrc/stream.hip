@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
 
   for (;;) {
     if (t == 0) s_word = atomicAdd(counter, 1);
-    __syncthreads();
+    lds_barrier();
     const int word = s_word;
     if (word >= B) break;  // same value in every thread
     const size_t base = (size_t)word * n;
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       const float mx = v2c_store(x, x <= 0.0f);
       for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = mx;
     }
-    __syncthreads();
+    lds_barrier();
 
     int it = 0;
     for (;;) {
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       }
       const unsigned long long b = __ballot(unsat);
       if ((t & 63) == 0) s_unsat[wave] = b != 0ull;
-      __syncthreads();
+      lds_barrier();
       int any_unsat = 0;
       for (int w = 0; w < W; ++w) any_unsat |= s_unsat[w];
       if ((early_stop && !any_unsat) || it == max_iters) break;  // same value in every thread
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         const bool z = acc <= 0.0f;
         var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = v2c_store(x, z); });
       }
-      __syncthreads();  // also orders this iteration's reads of s_unsat before the next writes
+      lds_barrier();  // also orders this iteration's reads of s_unsat before the next writes
       ++it;
     }
 
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       hard[base + v] = x <= 0.0f ? 1 : 0;
     }
     if (t == 0) iters[word] = it;
-    __syncthreads();  // L, s_word and s_unsat are reused by the next word
+    lds_barrier();  // L, s_word and s_unsat are reused by the next word
   }
 }
 

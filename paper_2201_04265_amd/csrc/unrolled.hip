@@ -317,21 +317,26 @@ __global__ void __launch_bounds__(512)
 __host__ __device__ inline size_t unrolled_lds_bwd_bytes(int64_t nnz, int32_t n) {
   return (size_t)nnz * 4 + (size_t)n * 4 + 16;
 }
-__host__ __device__ inline size_t unrolled_lds_fwd_bytes(int64_t nnz) { return (size_t)nnz * 4 + 16; }
+// Forward: the messages, plus the current iteration's weight row when it fits too
+// (staged once per iteration by coalesced reads instead of gathered per edge).
+__host__ __device__ inline size_t unrolled_lds_fwd_bytes(int64_t nnz, bool stage_w) {
+  return (size_t)nnz * (stage_w ? 8 : 4) + 16;
+}
 // Words per backward workgroup: a function of the batch only, so that the summation
 // order of the weight gradients does not depend on the device.
 __host__ __device__ inline int unrolled_lds_words_per_group(int32_t batch) {
   return batch <= 2048 ? 1 : (batch + 2047) / 2048;
 }
 
-template <int DC, int DV>
+template <int DC, int DV, bool STAGE_W>
 __global__ void __launch_bounds__(512)
     unrolled_fwd_lds(GraphDev g, const float *__restrict__ llr, const float *__restrict__ w, int B, int T,
                      float *__restrict__ ckpt, float *__restrict__ post) {
   constexpr int DVM = DV > 0 ? DV : -DV;
   constexpr int DCM = DC > 0 ? DC : -DC;
   extern __shared__ __align__(16) float smem[];
-  float *X = smem;  // A^(t) before the check phase, E^(t) after it
+  float *X = smem;                 // A^(t) before the check phase, E^(t) after it
+  float *Wl = smem + g.nnz;        // weight row of the iteration (when staged)
   const int tid = threadIdx.x, NT = blockDim.x;
   const int word = blockIdx.x;
   const size_t n = (size_t)g.n, E = (size_t)g.nnz;
@@ -344,7 +349,7 @@ __global__ void __launch_bounds__(512)
     for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = r;
     if (T == 0) out[v] = r;
   }
-  __syncthreads();
+  lds_barrier();
   for (int t = 1; t <= T; ++t) {
     float *Ck = ckpt + ((size_t)word * T + (t - 1)) * E;
     for (int c = tid; c < g.m; c += NT) {
@@ -362,8 +367,10 @@ __global__ void __launch_bounds__(512)
       check_core<DC>(mv, dc, ev);
       lds_row_store<DC>(X + e0, dc, ev);
     }
-    __syncthreads();
     const float *wt = w + (size_t)(t - 1) * E;
+    if (STAGE_W)
+      for (int e = tid; e < g.nnz; e += NT) Wl[e] = wt[e];
+    lds_barrier();
     for (int v = tid; v < g.n; v += NT) {
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
@@ -373,7 +380,7 @@ __global__ void __launch_bounds__(512)
       for (int j = 0; j < DVM; ++j) {
         if (DV > 0 || j < dv) {
           eid[j] = g.var_edges[p0 + j];
-          ev[j] = wt[eid[j]] * X[eid[j]];
+          ev[j] = (STAGE_W ? Wl[eid[j]] : wt[eid[j]]) * X[eid[j]];
         }
       }
       float acc = R[v];
@@ -389,7 +396,7 @@ __global__ void __launch_bounds__(512)
       else
         out[v] = acc;
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -416,7 +423,25 @@ __global__ void __launch_bounds__(512)
       dR[v] = gl;
       for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = gl;
     }
-    __syncthreads();
+    lds_barrier();
+    // The global inputs of a thread's first check (its checkpoint row, weights and
+    // weight-gradient row) are fetched one iteration ahead, during the variable phase.
+    float nav[DCM], nwt[DCM], nwp[DCM];
+    auto fetch = [&](int tt) {
+      if (tid >= g.m || tt < 1) return;
+      int e0, dc;
+      check_range<DC>(g, tid, e0, dc);
+      const size_t off = (size_t)(tt - 1) * E + (size_t)e0;
+#pragma unroll
+      for (int j = 0; j < DCM; ++j) {
+        if (DC > 0 || j < dc) {
+          nav[j] = ckpt[(size_t)word * T * E + off + j];
+          nwt[j] = w[off + j];
+          nwp[j] = k == 0 ? 0.0f : wp[off + j];
+        }
+      }
+    };
+    fetch(T);
     for (int t = T; t >= 1; --t) {
       const float *Ck = ckpt + ((size_t)word * T + (t - 1)) * E;
       const float *wt = w + (size_t)(t - 1) * E;
@@ -424,11 +449,14 @@ __global__ void __launch_bounds__(512)
       for (int c = tid; c < g.m; c += NT) {
         int e0, dc;
         check_range<DC>(g, c, e0, dc);
-        float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], gg[DCM], sh[DCM], qv[DCM], rv[DCM];
+        const bool first = c == tid;
+        float av[DCM], mv[DCM], ev[DCM], tau[DCM], a[DCM], gg[DCM], sh[DCM], qv[DCM], rv[DCM], wv[DCM], old[DCM];
 #pragma unroll
         for (int j = 0; j < DCM; ++j) {
           if (DC > 0 || j < dc) {
-            av[j] = Ck[e0 + j];
+            av[j] = first ? nav[j] : Ck[e0 + j];
+            wv[j] = first ? nwt[j] : wt[e0 + j];
+            old[j] = first ? nwp[j] : (k == 0 ? 0.0f : wpt[e0 + j]);
             mv[j] = clamp_msg(av[j]);
           }
         }
@@ -438,15 +466,16 @@ __global__ void __launch_bounds__(512)
         for (int j = 0; j < DCM; ++j) {
           if (DC > 0 || j < dc) {
             const float contrib = gg[j] * ev[j];
-            wpt[e0 + j] = k == 0 ? contrib : wpt[e0 + j] + contrib;
+            wpt[e0 + j] = k == 0 ? contrib : old[j] + contrib;
             float ch;
             adjoint_factors(mv[j], qv[j], rv[j], tau[j], sh[j], ch);
-            a[j] = gg[j] * wt[e0 + j] * ch;
+            a[j] = gg[j] * wv[j] * ch;
           }
         }
         check_adjoint<DC>(av, sh, tau, a, dc, [&](int j, float da) { X[e0 + j] = da; });
       }
-      __syncthreads();
+      lds_barrier();
+      fetch(t - 1);
       for (int v = tid; v < g.n; v += NT) {
         int p0, dv;
         var_range<DV>(g, v, p0, dv);
@@ -479,10 +508,10 @@ __global__ void __launch_bounds__(512)
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     for (int v = tid; v < g.n; v += NT) grad_llr[(size_t)word * n + v] = dR[v];
-    __syncthreads();  // dR and X are reused by the next word
+    lds_barrier();  // dR and X are reused by the next word
   }
 }
 
@@ -603,11 +632,12 @@ extern "C" ldpc_status ldpc_unrolled_forward(ldpc_graph_t g, const float *llr, c
   st = check_buffers(batch, T, llr, posterior, w, workspace, ws_bytes, fw, ckpt, ckpt_bytes, ck);
   if (st != LDPC_OK || batch == 0) return st;
   if (use_lds_form(g)) {
+    const bool stage_w = unrolled_lds_fwd_bytes(g->nnz, true) + 64 <= (size_t)lds_limit(g);
     LdsFwdKernel kl = nullptr;
-#define LDPC_PICK(C, V) kl = unrolled_fwd_lds<C, V>
+#define LDPC_PICK(C, V) kl = stage_w ? unrolled_fwd_lds<C, V, true> : unrolled_fwd_lds<C, V, false>
     LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
 #undef LDPC_PICK
-    const size_t lds = unrolled_lds_fwd_bytes(g->nnz);
+    const size_t lds = unrolled_lds_fwd_bytes(g->nnz, stage_w);
     if (lds > 65536)
       LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kl, dim3((unsigned)batch), dim3(lds_form_threads(g)), lds, stream, graph_dev(g), llr, w,
