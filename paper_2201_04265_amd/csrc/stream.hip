@@ -16,10 +16,11 @@
 //                 leaves the c->v message (Eq. 5); the variable phase reads that and
 //                 leaves the next v->c message.  Each edge is touched by its own
 //                 check, then by its own variable.
-//   L [n]   FP32  posterior of the last variable phase (Eq. 7)
-// The channel LLRs are re-read from the caller's buffer in every variable phase
-// (a coalesced read that stays in L2), which keeps a (3,6) n=4096 word at 64 KB so
-// that two words share a compute unit and one's barriers overlap the other's work.
+// The channel LLRs are re-read from the caller's buffer in every variable phase and the
+// posterior of each variable phase (Eq. 7) goes straight to the caller's output row
+// (both coalesced, and the rewrites of a row stay in L2), so a word needs 4 bytes of
+// LDS per edge: 48 KB for (3,6) n=4096, three words per compute unit, and codes up to
+// about 40 000 edges fit.
 // The check phase tests the syndrome of the decisions its messages carry (Eq. 1)
 // while it computes new messages.  Per edge the arithmetic and its order are those
 // of the plain decoder, so the outputs are identical to it bit for bit.
@@ -29,7 +30,8 @@
 namespace ldpc {
 
 __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
-  return (size_t)nnz * 4 + (size_t)n * 4 + 16;
+  (void)n;
+  return (size_t)nnz * 4 + 16;
 }
 
 // Workgroup size limit per degree pair: the generic kernels for check degrees above 8
@@ -49,7 +51,6 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
   __shared__ int s_word;
   __shared__ int s_unsat[16];  // per wavefront: some check of the word is unsatisfied
   float *X = smem;
-  float *L = X + g.nnz;
   const int t = threadIdx.x, NT = blockDim.x;
   const int wave = wave_id(), W = NT >> 6;
   const size_t n = (size_t)g.n;
@@ -61,10 +62,10 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     if (word >= B) break;  // same value in every thread
     const size_t base = (size_t)word * n;
 
-    // ingest: L = channel LLRs, first messages X = clamp(R), channel decisions
+    // ingest: posterior = channel LLRs, first messages X = clamp(R), channel decisions
     for (int v = t; v < g.n; v += NT) {
       const float x = llr64 ? (float)llr64[base + v] : llr32[base + v];
-      L[v] = x;
+      post[base + v] = x;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
       const float mx = v2c_store(x, x <= 0.0f);
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
             acc += ev[j];
           }
         }
-        L[v] = acc;
+        post[base + v] = acc;
         const bool z = acc <= 0.0f;
         var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = v2c_store(x, z); });
       }
@@ -131,13 +132,9 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       ++it;
     }
 
-    for (int v = t; v < g.n; v += NT) {
-      const float x = L[v];
-      post[base + v] = x;
-      hard[base + v] = x <= 0.0f ? 1 : 0;
-    }
+    for (int v = t; v < g.n; v += NT) hard[base + v] = post[base + v] <= 0.0f ? 1 : 0;  // own writes
     if (t == 0) iters[word] = it;
-    lds_barrier();  // L, s_word and s_unsat are reused by the next word
+    lds_barrier();  // X, s_word and s_unsat are reused by the next word
   }
 }
 
