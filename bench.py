@@ -216,23 +216,16 @@ def bench_c4(args, torch, P):
     ms_batched = time_launches(torch, lambda: batch.run(True, shape, ws), args.steps, args.warmup, stream)
     plan = P.Plan(batch, True, shape)
     ms_plan = time_launches(torch, lambda: plan.launch(), args.steps, args.warmup, stream)
-    # hybrid: codes whose word state fits LDS decoded by the stream form (one launch each),
-    # the others in one batched launch
-    fits = [P.stream_supported(g) for g in graphs]
-    rest = [i for i, f in enumerate(fits) if not f]
-    rest_batch = P.Batch([graphs[i] for i in rest], [llrs[i] for i in rest], MAX_ITERS) if rest else None
-    rest_shape = (P.Shape.make() if args.no_autotune else P.tuned_shape(rest_batch, True)) if rest else None
-    rest_ws = rest_batch.workspace(rest_shape) if rest else None
-    sws = torch.empty((256,), dtype=torch.uint8, device="cuda")
-    souts = [(torch.empty(x.shape, dtype=torch.uint8, device="cuda"), torch.empty(x.shape, device="cuda"),
-              torch.empty((x.shape[0],), dtype=torch.int32, device="cuda")) for x in llrs]
+    # the same batched call with the codes whose word state fits LDS in the stream form
+    hshape = P.Shape.make(resolved.waves, [resolved.slots[i] for i in range(len(codes))], resolved.refill,
+                          stream_codes=P.STREAM_AUTO)
+    hbatch = P.Batch(graphs, llrs, MAX_ITERS)
+    hresolved, _ = hbatch.resolve(hshape)
+    hws = hbatch.workspace(hshape)
+    fits = [bool((hresolved.stream_codes >> i) & 1) for i in range(len(codes))]
 
     def hybrid():
-        for i, f in enumerate(fits):
-            if f:
-                P.decode_stream(graphs[i], llrs[i], MAX_ITERS, True, workspace=sws, out=souts[i])
-        if rest:
-            rest_batch.run(True, rest_shape, rest_ws)
+        hbatch.run(True, hshape, hws)
 
     ms_hybrid = time_launches(torch, hybrid, args.steps, args.warmup, stream)
     bits = sum(int(x.numel()) for x in llrs)
@@ -242,24 +235,27 @@ def bench_c4(args, torch, P):
     for i, c in enumerate(codes):
         bo, po = batch.outs[i], pouts[i]
         same &= all(bool(torch.equal(a, b)) for a, b in zip(bo, po))
-        ho = souts[i] if fits[i] else rest_batch.outs[rest.index(i)]
-        same &= all(bool(torch.equal(a, b)) for a, b in zip(ho, po))
+        same &= all(bool(torch.equal(a, b)) for a, b in zip(hbatch.outs[i], po))
         per_code.append({"code": c.name, "n": c.n, "edges": c.nnz, "words": counts[i], "ebn0_db": float(ebn0[i]),
                          "mean_iters": float(bo[2].float().mean().item()),
                          "ber_coded": float((bo[0] != cws[i]).float().mean().item()),
                          "ber_coded_plain": float((po[0] != cws[i]).float().mean().item())})
     avg = lambda v: sum(v) / len(v)  # noqa: E731
     return {"metric": "coded Gbit/s, mixed six-code batch (4096 words); batched vs per-code plain launches",
-            "value": bits / (avg(ms_batched) * 1e-3) / 1e9, "unit": "coded Gbit/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": avg(ms_batched), "higher_is_better": True,
+            "value": bits / (avg(ms_hybrid) * 1e-3) / 1e9, "unit": "coded Gbit/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": avg(ms_hybrid), "higher_is_better": True,
+            "value_form": "batched call with the codes that fit LDS in the stream form (one launch each) and the "
+                          "rest in one persistent launch",
+            "persistent_only_gbit_s": bits / (avg(ms_batched) * 1e-3) / 1e9,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "4096 words round-robin over six seeded codes, each at its own Eb/N0 in [1,4] dB, "
                                    "max 50 iterations, early stop"},
             "batched_ms": avg(ms_batched), "batched_plan_ms": avg(ms_plan), "per_code_plain_ms": avg(ms_plain),
             "speedup_vs_per_code_plain": avg(ms_plain) / avg(ms_batched),
-            "hybrid_stream_plus_batched_ms": avg(ms_hybrid),
-            "hybrid_stream_codes": [codes[i].name for i, f in enumerate(fits) if f],
-            "hybrid_coded_gbit_s": bits / (avg(ms_hybrid) * 1e-3) / 1e9,
+            "batched_with_stream_codes_ms": avg(ms_hybrid),
+            "stream_codes": [codes[i].name for i, f in enumerate(fits) if f],
+            "batched_with_stream_codes_gbit_s": bits / (avg(ms_hybrid) * 1e-3) / 1e9,
+            "speedup_with_stream_codes_vs_per_code_plain": avg(ms_plain) / avg(ms_hybrid),
             "edge_updates_per_s": useful / (avg(ms_batched) * 1e-3), "shape": resolved.as_dict(len(codes)),
             "outputs_bitwise_equal": same, "per_code": per_code}
 

@@ -149,14 +149,21 @@ typedef struct {
  * (workgroups) per code (0 = automatic: the resident capacity of the GPU shared
  * in proportion to words x edges, at most one slot per 64 words); refill: a slot
  * writes out and replaces its stopped words once this many of its 64 lanes wait
- * (0 = 1), or when none is still running. */
+ * (0 = 1), or when none is still running.  stream_codes: bit q set = code q is
+ * decoded by the stream form instead (one word per workgroup, state in LDS, its own
+ * launch before the persistent one; same outputs bit for bit; the code's word
+ * state must fit, see ldpc_stream_lds_bytes, else LDPC_ERR_UNSUPPORTED);
+ * LDPC_STREAM_AUTO = every code whose word state fits; 0 = none. */
+#define LDPC_STREAM_AUTO 0xFFFFFFFFu
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];
   int32_t refill;
+  uint32_t stream_codes;
 } ldpc_multi_shape;
 
-/* Shape ldpc_decode_multi would use (automatic slot counts filled in) and its workspace size. */
+/* Shape ldpc_decode_multi would use (automatic slot counts and the stream mask filled
+ * in; codes in stream form get 0 slots) and its workspace size. */
 ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                const ldpc_multi_shape *shape, ldpc_multi_shape *resolved, size_t *ws_bytes);
 

@@ -13,5 +13,5 @@ from __future__ import annotations
 from ._lib import LdpcError, lib, library_path  # noqa: F401
 from .graph import Graph  # noqa: F401
 from .decoder import decode, decode_stream, stream_supported, workspace_size  # noqa: F401
-from .multi import Batch, Plan, Shape, decode_multi, tuned_shape  # noqa: F401
+from .multi import STREAM_AUTO, Batch, Plan, Shape, decode_multi, tuned_shape  # noqa: F401
 from .unrolled import UnrolledBP, unrolled_decode  # noqa: F401

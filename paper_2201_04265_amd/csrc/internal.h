@@ -119,4 +119,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch,
                                 int32_t max_iters, int32_t early_stop, uint8_t *hard, float *post, int32_t *iters,
                                 void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream);
+// Stream form (stream.hip): readiness of a graph for it (device facts cached; an error
+// if its word state exceeds LDS) and one enqueued decode using `counter` (device int).
+ldpc_status stream_ready_for(ldpc_graph_s *g, int32_t threads);
+ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch, int32_t max_iters,
+                                 int32_t early_stop, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
+                                 int *counter, int32_t threads, hipStream_t stream);
 size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch);

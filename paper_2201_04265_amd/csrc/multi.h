@@ -33,6 +33,15 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
 // Lays the jobs out over the workspace.
 ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs, const int32_t *const *orders,
                        const ldpc_multi_shape &sh, void *ws, MultiArgs *a, int **counters, int *grid);
-// Enqueues the counter reset and the persistent launch.
+// Codes of a batched decode that run in the stream form (host side).
+struct StreamCodes {
+  int n = 0;
+  int code[LDPC_MAX_CODES];
+  ldpc_graph_s *g[LDPC_MAX_CODES];
+  ldpc_job job[LDPC_MAX_CODES];
+};
+
+// Enqueues the stream-form decodes (counters at counters + 64 + code), the counter reset
+// and the persistent launch.
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
-                          hipStream_t stream);
+                          hipStream_t stream, const StreamCodes *sc);

@@ -202,14 +202,20 @@ MultiKernel pick_single(int32_t kind) {
 
 }  // namespace
 
+// The kernel for the codes that have slots (codes decoded elsewhere, e.g. in the stream
+// form, do not force the generic mixed kernel on the others).
 MultiKernel multi_kernel_for(const MultiArgs &a) {
+  bool any = false;
+  for (int i = 0; i < a.njobs; ++i) any |= a.jobs[i].nslots > 0;
   bool same = true;
-  int dcmax = 0;
+  int dcmax = 0, kind = -1;
   for (int i = 0; i < a.njobs; ++i) {
-    same &= a.jobs[i].kind == a.jobs[0].kind;
+    if (any && a.jobs[i].nslots == 0) continue;
+    if (kind < 0) kind = a.jobs[i].kind;
+    same &= a.jobs[i].kind == kind;
     dcmax = std::max(dcmax, a.jobs[i].dc_max);
   }
-  if (same) return pick_single(a.jobs[0].kind);
+  if (same) return pick_single(kind);
   if (dcmax <= 16) return multi_kernel_mixed<-16>;
   if (dcmax <= 24) return multi_kernel_mixed<-24>;
   return multi_kernel_mixed<-LDPC_MAX_CHECK_DEGREE>;
@@ -221,26 +227,41 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     return set_error(LDPC_ERR_INVALID_ARG, "need 1.." + std::to_string(LDPC_MAX_CODES) + " codes");
   ldpc_multi_shape sh{};
   if (shape_in) sh = *shape_in;
+  for (int q = 0; q < ncodes; ++q)
+    if (!graphs[q]) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
+  // codes decoded by the stream form: requested ones must fit, AUTO takes those that do
+  uint32_t mask = 0;
+  for (int q = 0; q < ncodes; ++q) {
+    if (!((sh.stream_codes >> q) & 1u)) continue;
+    const ldpc_status st = stream_ready_for(graphs[q], 0);
+    if (st == LDPC_OK)
+      mask |= 1u << q;
+    else if (sh.stream_codes != LDPC_STREAM_AUTO || st != LDPC_ERR_UNSUPPORTED)
+      return st;
+  }
+  sh.stream_codes = mask;
+  for (int q = 0; q < ncodes; ++q)
+    if ((mask >> q) & 1u) sh.slots[q] = 0;
   if (sh.waves == 0) {
     // small batches (fewer 64-word tiles than compute units) get the widest workgroups
     int dev = 0, cus = 0;
     LDPC_HIP_CHECK(hipGetDevice(&dev));
     LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     long tiles = 0;
-    for (int q = 0; q < ncodes; ++q) tiles += (jobs[q].batch + TW - 1) / TW;
+    for (int q = 0; q < ncodes; ++q)
+      if (!((mask >> q) & 1u)) tiles += (jobs[q].batch + TW - 1) / TW;
     sh.waves = tiles < cus ? 16 : 8;
   }
   if (sh.waves < 1 || sh.waves > 16) return set_error(LDPC_ERR_INVALID_ARG, "waves must be in 1..16");
   if (sh.refill == 0) sh.refill = 1;
   if (sh.refill < 1 || sh.refill > kTile) return set_error(LDPC_ERR_INVALID_ARG, "refill must be in 1..64");
   for (int q = 0; q < ncodes; ++q) {
-    if (!graphs[q]) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
     if (jobs[q].batch < 0 || jobs[q].max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative batch/max_iters");
     if (sh.slots[q] < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative slot count");
   }
   // automatic slot counts: fill the resident capacity, shared in proportion to words x edges
   bool need_auto = false;
-  for (int q = 0; q < ncodes; ++q) need_auto |= sh.slots[q] == 0 && jobs[q].batch > 0;
+  for (int q = 0; q < ncodes; ++q) need_auto |= sh.slots[q] == 0 && jobs[q].batch > 0 && !((mask >> q) & 1u);
   if (need_auto) {
     int dev = 0, cus = 0;
     LDPC_HIP_CHECK(hipGetDevice(&dev));
@@ -250,21 +271,23 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     for (int q = 0; q < ncodes; ++q) {
       probe.jobs[q].kind = kernel_kind(graphs[q]);
       probe.jobs[q].dc_max = graphs[q]->dc_max;
+      probe.jobs[q].nslots = jobs[q].batch > 0 && !((mask >> q) & 1u) ? 1 : 0;
     }
     int per_cu = 0;
     LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)multi_kernel_for(probe),
                                                                 64 * sh.waves, 0));
     const double cap = (double)cus * (per_cu > 0 ? per_cu : 1);
     double total = 0;
-    for (int q = 0; q < ncodes; ++q) total += (double)jobs[q].batch * (double)graphs[q]->nnz;
+    for (int q = 0; q < ncodes; ++q)
+      if (!((mask >> q) & 1u)) total += (double)jobs[q].batch * (double)graphs[q]->nnz;
     for (int q = 0; q < ncodes; ++q) {
-      if (sh.slots[q] != 0 || jobs[q].batch == 0) continue;
+      if (sh.slots[q] != 0 || jobs[q].batch == 0 || ((mask >> q) & 1u)) continue;
       const int tiles = (jobs[q].batch + TW - 1) / TW;
       int s = (int)(cap * (double)jobs[q].batch * (double)graphs[q]->nnz / total + 0.5);
       sh.slots[q] = std::max(1, std::min(s, tiles));
     }
   }
-  size_t bytes = 256;  // counters
+  size_t bytes = 512;  // counters of the persistent launch, then of the stream-form codes
   for (int q = 0; q < ncodes; ++q) {
     if (jobs[q].batch == 0) sh.slots[q] = 0;
     bytes += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
@@ -278,7 +301,7 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
                        const ldpc_multi_shape &sh, void *ws, MultiArgs *a, int **counters, int *grid) {
   char *p = (char *)ws;
   *counters = (int *)p;
-  p += 256;
+  p += 512;
   a->njobs = ncodes;
   a->refill_min = sh.refill;
   int slot = 0;
@@ -308,7 +331,15 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
 }
 
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
-                          hipStream_t stream) {
+                          hipStream_t stream, const StreamCodes *sc) {
+  if (sc) {
+    for (int i = 0; i < sc->n; ++i) {
+      const ldpc_job &j = sc->job[i];
+      ldpc_status st = launch_stream_decode(sc->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
+                                            j.posterior, j.iters_used, counters + 64 + sc->code[i], 0, stream);
+      if (st != LDPC_OK) return st;
+    }
+  }
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counters, a.njobs);
   LDPC_HIP_CHECK(hipGetLastError());
   if (grid == 0) return LDPC_OK;

@@ -13,7 +13,8 @@ extern "C" ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t nc
 
 static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                  const int32_t *const *orders, const ldpc_multi_shape *shape, void *ws,
-                                 size_t ws_bytes, MultiArgs *a, int **counters, int *grid, int *waves) {
+                                 size_t ws_bytes, MultiArgs *a, int **counters, int *grid, int *waves,
+                                 StreamCodes *sc) {
   ldpc_multi_shape sh;
   size_t need = 0;
   ldpc_status st = multi_resolve(graphs, ncodes, jobs, shape, &sh, &need);
@@ -22,6 +23,17 @@ static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, con
   if (((uintptr_t)ws & 255) != 0) return set_error(LDPC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (ws_bytes < need) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small");
   *waves = sh.waves;
+  sc->n = 0;
+  for (int q = 0; q < ncodes; ++q) {
+    if (!((sh.stream_codes >> q) & 1u) || jobs[q].batch == 0) continue;
+    const ldpc_job &j = jobs[q];
+    if (!j.llr || !j.hard_bits || !j.posterior || !j.iters_used)
+      return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer in job " + std::to_string(q));
+    sc->code[sc->n] = q;
+    sc->g[sc->n] = graphs[q];
+    sc->job[sc->n] = j;
+    ++sc->n;
+  }
   return multi_args(graphs, ncodes, jobs, orders, sh, ws, a, counters, grid);
 }
 
@@ -30,12 +42,13 @@ extern "C" ldpc_status ldpc_decode_multi(const ldpc_graph_t *graphs, int32_t nco
                                          const ldpc_multi_shape *shape, void *workspace, size_t ws_bytes,
                                          hipStream_t stream) {
   MultiArgs a{};
+  StreamCodes sc;
   int *counters = nullptr;
   int grid = 0, waves = 0;
   ldpc_status st = multi_prepare(graphs, ncodes, jobs, orders, shape, workspace, ws_bytes, &a, &counters, &grid,
-                                 &waves);
+                                 &waves, &sc);
   if (st != LDPC_OK) return st;
-  return multi_enqueue(a, counters, grid, waves, early_stop, stream);
+  return multi_enqueue(a, counters, grid, waves, early_stop, stream, &sc);
 }
 
 struct ldpc_plan_s {
@@ -51,10 +64,11 @@ extern "C" ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_
   *out = nullptr;
   if (!capture_stream) return set_error(LDPC_ERR_INVALID_ARG, "capture needs a non-default stream");
   MultiArgs a{};
+  StreamCodes sc;
   int *counters = nullptr;
   int grid = 0, waves = 0;
   ldpc_status st = multi_prepare(graphs, ncodes, jobs, orders, shape, workspace, ws_bytes, &a, &counters, &grid,
-                                 &waves);
+                                 &waves, &sc);
   if (st != LDPC_OK) return st;
   ldpc_plan_s *p = new (std::nothrow) ldpc_plan_s();
   if (!p) return set_error(LDPC_ERR_OUT_OF_MEMORY, "plan allocation");
@@ -63,7 +77,7 @@ extern "C" ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_
     delete p;
     return hip_error(e, "hipStreamBeginCapture");
   }
-  st = multi_enqueue(a, counters, grid, waves, early_stop, capture_stream);
+  st = multi_enqueue(a, counters, grid, waves, early_stop, capture_stream, &sc);
   e = hipStreamEndCapture(capture_stream, &p->graph);
   if (st != LDPC_OK || e != hipSuccess) {
     if (p->graph) (void)hipGraphDestroy(p->graph);

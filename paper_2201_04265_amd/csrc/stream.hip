@@ -230,6 +230,50 @@ extern "C" ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int3
   return LDPC_OK;
 }
 
+ldpc_status stream_ready_for(ldpc_graph_s *g, int32_t threads) {
+  int max_threads = 1024;
+  StreamKernel k = pick_stream(g, max_threads);
+  if (threads > max_threads)
+    return set_error(LDPC_ERR_INVALID_ARG,
+                     "threads above " + std::to_string(max_threads) + " for this code's check degree");
+  const size_t lds = stream_lds_bytes(g->nnz, g->n);
+  ldpc_status st = stream_prepare(g, k, max_threads, lds);
+  if (st != LDPC_OK) return st;
+  if (lds + 64 > (size_t)g->stream_lds_limit)
+    return set_error(LDPC_ERR_UNSUPPORTED, "word state (" + std::to_string(lds) + " bytes) exceeds LDS");
+  return LDPC_OK;
+}
+
+ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch, int32_t max_iters,
+                                 int32_t early_stop, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
+                                 int *counter, int32_t threads, hipStream_t stream) {
+  ldpc_status st = stream_ready_for(g, threads);
+  if (st != LDPC_OK) return st;
+  if (batch == 0) return LDPC_OK;
+  int max_threads = 1024;
+  StreamKernel k = pick_stream(g, max_threads);
+  const size_t lds = stream_lds_bytes(g->nnz, g->n);
+  const int nt = threads ? threads : stream_threads(g, max_threads, batch);
+  if (nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  int per_cu = 0;
+  if ((nt & (nt - 1)) == 0) {  // powers of two: resident counts known
+    int lg = 0;
+    while ((64 << lg) < nt) ++lg;
+    per_cu = g->stream_per_cu[lg];
+  } else {
+    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
+  }
+  if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
+  const int grid = std::min(batch, g->stream_cus * per_cu);
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, counter);
+  LDPC_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, stream, graph_dev(g),
+                     llr_f64 ? nullptr : (const float *)llr, llr_f64 ? (const double *)llr : nullptr, (int)batch,
+                     (int)max_iters, (int)(early_stop != 0), counter, hard_bits, posterior, iters_used);
+  LDPC_HIP_CHECK(hipGetLastError());
+  return LDPC_OK;
+}
+
 extern "C" ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
                                           int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
                                           int32_t *iters_used, void *workspace, size_t ws_bytes, int32_t threads,
@@ -243,35 +287,6 @@ extern "C" ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32
   if (!llr || !hard_bits || !posterior || !iters_used || !workspace)
     return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
   if (ws_bytes < 256) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small (256 bytes)");
-  const size_t lds = stream_lds_bytes(g->nnz, g->n);
-  int max_threads = 1024;
-  StreamKernel k = pick_stream(g, max_threads);
-  if (threads > max_threads)
-    return set_error(LDPC_ERR_INVALID_ARG,
-                     "threads above " + std::to_string(max_threads) + " for this code's check degree");
-  ldpc_status st = stream_prepare(g, k, max_threads, lds);
-  if (st != LDPC_OK) return st;
-  if (lds + 64 > (size_t)g->stream_lds_limit)
-    return set_error(LDPC_ERR_UNSUPPORTED, "word state (" + std::to_string(lds) + " bytes) exceeds LDS");
-  const int nt = threads ? threads : stream_threads(g, max_threads, batch);
-  if (nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
-  int per_cu = 0;
-  if ((nt & (nt - 1)) == 0) {  // powers of two: resident counts known
-    int lg = 0;
-    while ((64 << lg) < nt) ++lg;
-    per_cu = g->stream_per_cu[lg];
-  } else {
-    LDPC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, nt, lds));
-  }
-  const int cus = g->stream_cus;
-  if (per_cu < 1) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
-  const int grid = std::min(batch, cus * per_cu);
-  int *counter = (int *)workspace;
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, counter);
-  LDPC_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, stream, graph_dev(g), (flags & LDPC_LLR_F64) ? nullptr : (const float *)llr,
-                     (flags & LDPC_LLR_F64) ? (const double *)llr : nullptr, (int)batch, (int)max_iters,
-                     (int)(early_stop != 0), counter, hard_bits, posterior, iters_used);
-  LDPC_HIP_CHECK(hipGetLastError());
-  return LDPC_OK;
+  return launch_stream_decode(g, llr, (flags & LDPC_LLR_F64) != 0, batch, max_iters, early_stop, hard_bits, posterior,
+                              iters_used, (int *)workspace, threads, stream);
 }

@@ -20,20 +20,28 @@ class Job(ctypes.Structure):
                 ("hard_bits", ctypes.c_void_p), ("posterior", ctypes.c_void_p), ("iters_used", ctypes.c_void_p)]
 
 
+STREAM_AUTO = 0xFFFFFFFF  # every code whose word state fits LDS runs in the stream form
+
+
 class Shape(ctypes.Structure):
-    _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32)]
+    _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32),
+                ("stream_codes", ctypes.c_uint32)]
 
     @classmethod
-    def make(cls, waves=0, slots=None, refill=0):
+    def make(cls, waves=0, slots=None, refill=0, stream_codes=0):
         s = cls()
         s.waves = int(waves)
         s.refill = int(refill)
+        s.stream_codes = int(stream_codes) & 0xFFFFFFFF
         for i, v in enumerate(slots or []):
             s.slots[i] = int(v)
         return s
 
     def as_dict(self, ncodes):
-        return {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill}
+        d = {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill}
+        if self.stream_codes:
+            d["stream_codes"] = [i for i in range(ncodes) if (self.stream_codes >> i) & 1]
+        return d
 
 
 class Batch:

@@ -152,3 +152,51 @@ def test_autotuner_picks_a_valid_shape(P, tmp_path, monkeypatch):
     assert again.waves == shape.waves and again.slots[0] == shape.slots[0]
     ref = _plain(P, [g], [x], 50)
     _same(ref, _np(batch.run(True, shape)))
+
+
+def test_c4_stream_codes_equal_per_code_plain(P, c4):
+    """Codes whose word state fits LDS run in the stream form inside the batched decode;
+    the outputs stay bit-identical to per-code plain launches."""
+    codes, graphs, words, llrs, _ = c4
+    ref = _plain(P, graphs, llrs, 50)
+    batch = P.Batch(graphs, llrs, 50)
+    shape = P.Shape.make(stream_codes=P.STREAM_AUTO)
+    resolved, _ = batch.resolve(shape)
+    fits = [P.stream_supported(g) for g in graphs]
+    assert fits == [c.nnz * 4 + 16 + 64 <= 160 * 1024 for c in codes]
+    for q in range(len(codes)):
+        assert bool((resolved.stream_codes >> q) & 1) == fits[q]
+        if fits[q]:
+            assert resolved.slots[q] == 0
+    _same(ref, _np(batch.run(True, shape)))
+    # a fixed-iteration run of only some codes in the stream form
+    ref7 = _plain(P, graphs, llrs, 7, False)
+    batch7 = P.Batch(graphs, llrs, 7)
+    _same(ref7, _np(batch7.run(False, P.Shape.make(8, stream_codes=0b000101))))
+
+
+def test_plan_with_stream_codes_replays_match_eager(P, c4):
+    codes, graphs, words, llrs, _ = c4
+    eager = _plain(P, graphs, llrs, 50)
+    batch = P.Batch(graphs, llrs, 50)
+    plan = P.Plan(batch, True, P.Shape.make(stream_codes=P.STREAM_AUTO))
+    for rep in range(3):
+        for o in batch.outs:
+            for t in o:
+                t.zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        _same(eager, _np(batch.outs))
+        P.decode(graphs[0], llrs[0], 20, True)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_stream_code_that_does_not_fit_is_unsupported(P, c4):
+    codes, graphs, words, llrs, _ = c4
+    big = [i for i, g in enumerate(graphs) if not P.stream_supported(g)]
+    assert big  # the n=16384 code
+    batch = P.Batch(graphs, llrs, 50)
+    with pytest.raises(P.LdpcError) as e:
+        batch.run(True, P.Shape.make(stream_codes=1 << big[0]))
+    assert e.value.status == -5
