@@ -42,11 +42,11 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "ba38e0087af2e11078ba4865ac854931e1f534f1", "bytes_per_launch": 12100100788, "read_bytes": 5369158132,
-               "write_bytes": 6730942656},
+               "sha1": "8817784709dc9b74c89d6e97c74c0fded0a64825", "bytes_per_launch": 87024511667, "read_bytes": 14830668979,
+               "write_bytes": 72193842688},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "0f5368ba58054f35c9b49187990e7d7b184699f7", "bytes_per_launch": 1639140048649, "read_bytes": 959011941929,
-                "write_bytes": 680128106720},
+                "sha1": "7c2bea205ce25c913fd31eb12371ca19eb20d9f4", "bytes_per_launch": 1639887337251, "read_bytes": 959615965763,
+                "write_bytes": 680271371488},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
@@ -79,8 +79,9 @@ def roofline(head, code, B):
                 "avg_launch_ms": head["ms_per_step"],
                 "unit_of_work": "useful edge-iteration x VALU issue slots per edge-iteration (%.2f, compiled "
                                 "code; half-rate transcendentals count 2)" % STREAM_VALU_SLOTS_PER_EDGE,
-                "traffic_note": "HBM bytes per launch: LLRs in, posteriors and decisions out (9n per word); "
-                                "messages stay in LDS",
+                "traffic_note": "HBM bytes per launch (counters): messages stay in LDS; beyond the 9n bytes of "
+                                "I/O per word, posterior rewrites of each iteration that overflow L2 (the "
+                                "kernel is VALU-bound; keeping them in LDS costs one resident word per CU)",
                 "hbm_alg_gb_s_equivalent": head["achieved_gb_s"]}
     return {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
