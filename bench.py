@@ -51,10 +51,10 @@ COUNTER_TRAFFIC = {
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
 # VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 99 VALU instructions per degree-6 check (18 of them exp2 / rcp / log2) and 28 per
-# degree-3 variable.  The transcendentals issue at half rate (two slots): the counters show
-# SQ_ACTIVE_INST_VALU x 4 = SQ_INSTS_VALU x 4 + SQ_INSTS_VALU_TRANS_F32 x 4 cycles.
-STREAM_VALU_SLOTS_PER_EDGE = (99 + 18) / 6.0 + 28 / 3.0
+# code: 99 VALU instructions per degree-6 check and 28 per degree-3 variable, one wave64
+# instruction = 64 lane-slots.  The counters show SQ_INSTS_VALU x 4 cycles = 98.7 % of the
+# SIMD cycles of the launch, so the exp2 / log2 / rcp among them (10 %) add no issue cycles.
+STREAM_VALU_SLOTS_PER_EDGE = 99 / 6.0 + 28 / 3.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 
@@ -77,8 +77,8 @@ def roofline(head, code, B):
         return {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": a / VALU_PEAK_TOPS,
                 "traffic": counter_traffic("stream", B), "kernel": head["kernel"],
                 "avg_launch_ms": head["ms_per_step"],
-                "unit_of_work": "useful edge-iteration x VALU issue slots per edge-iteration (%.2f, compiled "
-                                "code; half-rate transcendentals count 2)" % STREAM_VALU_SLOTS_PER_EDGE,
+                "unit_of_work": "useful edge-iteration x VALU instructions per edge-iteration (%.2f lane-slots, "
+                                "compiled code)" % STREAM_VALU_SLOTS_PER_EDGE,
                 "traffic_note": "HBM bytes per launch (counters): messages stay in LDS; beyond the 9n bytes of "
                                 "I/O per word, posterior rewrites of each iteration that overflow L2 (the "
                                 "kernel is VALU-bound; keeping them in LDS costs one resident word per CU)",
