@@ -80,8 +80,11 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
                                                float *ar = nullptr) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
-  // qs[j] = q_j with M_j's sign bit, so that the messages themselves are not kept
+  // qs[j] = q_j, and the sign of M_j: for degrees up to 16 the message's bit pattern is
+  // kept (mb); above, the sign bit rides in qs[j] so that the messages need not stay live.
+  constexpr bool KEEP_BITS = FIXED && DMAX <= 16;
   float qs[DMAX], pd[DMAX], ps[DMAX];
+  uint32_t mb[KEEP_BITS ? DMAX : 1];
   uint32_t sx = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
@@ -90,7 +93,12 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
       sx ^= b;
       const float q = STORED ? __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown))
                              : __builtin_amdgcn_exp2f(-fabsf(mv[j]) * kL2e);
-      qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
+      if (KEEP_BITS) {
+        mb[KEEP_BITS ? j : 0] = b;
+        qs[j] = q;
+      } else {
+        qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
+      }
     }
   }
   // Joins with the empty set (0, 1) are written out: they are exact, and 0 * x cannot
@@ -141,7 +149,7 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
         aq[j] = fabsf(qs[j]);
         ar[j] = fmaxf(ratio, 1.0f);
       }
-      const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
+      const uint32_t sgn = (sx ^ (KEEP_BITS ? mb[KEEP_BITS ? j : 0] : __float_as_uint(qs[j]))) & 0x80000000u;
       eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
       const float q = fabsf(qs[j]);
       if (top) {
