@@ -200,3 +200,15 @@ def test_stream_code_that_does_not_fit_is_unsupported(P, c4):
     with pytest.raises(P.LdpcError) as e:
         batch.run(True, P.Shape.make(stream_codes=1 << big[0]))
     assert e.value.status == -5
+
+
+def test_orders_with_stream_codes(P, c4):
+    """A word order only changes the schedule: with some codes in the stream form (which takes
+    words in its own order) the outputs still equal per-code plain decoding."""
+    codes, graphs, words, llrs, _ = c4
+    ref = _plain(P, graphs, llrs, 30)
+    orders = [torch.randperm(x.shape[0], generator=torch.Generator().manual_seed(q)).to(torch.int32).cuda()
+              for q, x in enumerate(llrs)]
+    out = P.decode_multi(graphs, llrs, 30, True, shape=P.Shape.make(stream_codes=P.STREAM_AUTO), orders=orders)
+    torch.cuda.synchronize()
+    _same(ref, _np(out))

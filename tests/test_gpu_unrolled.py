@@ -159,3 +159,36 @@ def test_batch_sizes_across_group_boundaries(P, c5):
     assert np.array_equal(small[1], a[1][:5])
     scale = 5 / 2051  # the loss is a mean over the batch
     assert np.allclose(small[2] * scale, a[2][:5], rtol=1e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_irregular_code_lds_form(P, seed):
+    """Irregular codes (generic-degree kernels) in the one-word-per-workgroup form: all-ones
+    weights equal the plain decoder bit for bit, and the adjoint matches the FP64 reference."""
+    from oracle import grad
+    from synth import codes
+
+    rng = np.random.default_rng(4100 + seed)
+    n = int(rng.integers(80, 200))
+    m = int(rng.integers(n // 4, n // 2))
+    chk, var = [], []
+    for c in range(m):
+        d = int(rng.integers(2, 14))
+        vs = rng.choice(n, size=d, replace=False)
+        chk += [c] * d
+        var += list(vs)
+    code = codes.from_edges(m, n, np.array(chk), np.array(var))
+    g = P.Graph.from_code(code)
+    T = 5
+    llr = rng.normal(1.5, 2.0, size=(37, n)).astype(np.float32)
+    x = torch.from_numpy(llr).cuda()
+    post_u = P.unrolled_decode(g, x, torch.ones((T, code.nnz), dtype=torch.float32, device="cuda"))
+    _, post_p, _ = P.decode(g, x, T, early_stop=False)
+    assert torch.equal(post_u, post_p)
+    w = rng.normal(1.0, 0.1, size=(T, code.nnz)).astype(np.float32)
+    cw = np.zeros((6, n), dtype=np.uint8)
+    loss_g, _, gl, gw = gpu_grads(P, g, llr[:6], w, cw)
+    loss_r, rl, rw = grad.reference_grad(code, llr[:6].astype(np.float64), w.astype(np.float64), cw)
+    assert loss_g == pytest.approx(loss_r, rel=1e-5)
+    for a, r in ((gw, rw), (gl, rl)):
+        assert np.linalg.norm(a - r) / np.linalg.norm(r) <= 1e-3
