@@ -42,11 +42,11 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "8817784709dc9b74c89d6e97c74c0fded0a64825", "bytes_per_launch": 87024511667, "read_bytes": 14830668979,
-               "write_bytes": 72193842688},
+               "sha1": "128df3013dc5c77e87100ea92aa4ea7b35193e52", "bytes_per_launch": 88500956258, "read_bytes": 15045516610,
+               "write_bytes": 73455439648},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "7c2bea205ce25c913fd31eb12371ca19eb20d9f4", "bytes_per_launch": 1639887337251, "read_bytes": 959615965763,
-                "write_bytes": 680271371488},
+                "sha1": "51ab6042e61a98df6aa1a4be42552e1c9a1e59fe", "bytes_per_launch": 1640417000363, "read_bytes": 960064611211,
+                "write_bytes": 680352389152},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
