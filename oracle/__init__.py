@@ -9,7 +9,9 @@ import it; the decoder package never does, and the two share no code.
 * ``unrolled``    -- the per-edge-weighted unrolled form (C, FP64);
 * ``syndrome_ok`` -- H z^T = 0 test (Eq. 1);
 * ``bitwise_map`` -- exact bitwise MAP by enumerating every codeword (map.py);
-* ``grad``        -- torch FP64 reference gradient and finite differences (grad.py).
+* ``grad``        -- torch FP64 reference gradient and finite differences (grad.py);
+* ``encode``      -- systematic GF(2) encoder from H (Eqs. 1-3), dense and direct (encode.py);
+* ``channel``     -- Philox4x64-10 message bits and Box-Muller AWGN LLRs (Eq. 4), numpy (channel.py).
 
 Every function takes a code as any object with ``m, n, indptr, indices`` (CSR
 of H, column indices ascending within each row).
