@@ -234,6 +234,80 @@ ldpc_status ldpc_unrolled_backward(ldpc_graph_t g, const float *w, const void *c
                                    const float *grad_post, int32_t batch, int32_t T, float *grad_llr, float *grad_w,
                                    void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---- word generation: systematic encoder, BPSK/AWGN channel, error counts -- */
+
+typedef struct ldpc_encoder_s *ldpc_encoder_t;
+
+/*
+ * Systematic encoder of the code of g.  Codewords are the words c with
+ * H c^T = 0 (Eq. 1), the row space of a generator G, and a message m of k bits
+ * is sent as c = m G (Eqs. 2-3); a systematic G copies m into k positions
+ * (the [I_k : P] form of Sec. III-B up to a column permutation).  The
+ * positions: H is reduced over GF(2) with pivot columns taken from the last
+ * column towards the first (the first remaining row with a 1 in a column becomes
+ * its pivot row); rank = number of pivots, k = n - rank; the non-pivot columns,
+ * ascending, carry the message (message bit j goes to info[j]) and the pivot
+ * column of reduced row r carries the parity of the message bits in that row.
+ * The reduction runs on the host at create (bit-packed rows; seconds for
+ * n ~ 16k).  The encoder holds device arrays on the current device (A: rank x
+ * ceil(k/64) 64-bit words, a column map of n int32) until destroyed and is
+ * independent of g afterwards.
+ */
+ldpc_status ldpc_encoder_create(ldpc_graph_t g, ldpc_encoder_t *out);
+ldpc_status ldpc_encoder_destroy(ldpc_encoder_t e);
+ldpc_status ldpc_encoder_info(ldpc_encoder_t e, int32_t *n, int32_t *k, int32_t *rank);
+/* Host outputs (each may be NULL): info [k] message positions, pivots [rank] the
+ * pivot column of reduced row r. */
+ldpc_status ldpc_encoder_positions(ldpc_encoder_t e, int32_t *info, int32_t *pivots);
+
+/*
+ * Codewords of caller messages: msg [batch][k] bytes (any nonzero byte is a 1),
+ * cw [batch][n] bytes 0/1 out, both device memory, cw 4-byte aligned.  One
+ * workgroup per 64 words keeps their messages (64 x 8 ceil(k/64) bytes) and
+ * parity bits (8 x rank bytes, rank rounded up to 4) in LDS; a code whose
+ * total exceeds the LDS of one workgroup gives LDPC_ERR_UNSUPPORTED.
+ */
+ldpc_status ldpc_encode(ldpc_encoder_t e, const uint8_t *msg, int32_t batch, uint8_t *cw, hipStream_t stream);
+
+/*
+ * BPSK over AWGN (Sec. II-B, Eq. 4 with lambda = log P(0)/P(1)): x = 1 - 2c,
+ * y = x + sigma z, lambda = 2 y / sigma^2, computed in FP64 and written as FP32
+ * (flags 0) or FP64 (LDPC_LLR_F64).  cw [batch][n] bytes (nonzero = 1) in, llr
+ * [batch][n] out (16-byte aligned), device memory.  The noise is counter-based
+ * (Philox4x64-10 of Salmon et al., SC 2011, then Box-Muller): word w = first_word
+ * + b, positions 4j..4j+3 take the block of counter (w, j, noise_stream, 0) under
+ * key (seed, 2); the pair (x0, x1) gives positions 4j (cosine) and 4j+1 (sine),
+ * (x2, x3) positions 4j+2 and 4j+3, with u1 = ((x0 >> 11) + 1) 2^-53 and
+ * u2 = (x1 >> 11) 2^-53, z = sqrt(-2 ln u1) (cos | sin)(2 pi u2).  Any block of
+ * words can be drawn on its own; noise_stream separates draws of the same words
+ * (one per Eb/N0 point, say).  sigma2 must be finite and > 0.
+ */
+ldpc_status ldpc_channel_awgn(const uint8_t *cw, int32_t batch, int32_t n, double sigma2, uint64_t seed,
+                              uint64_t noise_stream, int64_t first_word, uint32_t flags, void *llr,
+                              hipStream_t stream);
+
+/*
+ * Random messages, their codewords and their channel LLRs in one launch.  The
+ * message bits of word w come from key (seed, 1), counter (w, j, 0, 0): block j
+ * gives bits 256 j .. 256 j + 255, bit i = bit (i mod 64) of output (i div 64)
+ * mod 4; they do not depend on noise_stream, so every Eb/N0 point of a sweep sees
+ * the same words.  Outputs cw [batch][n] and llr [batch][n] as in
+ * ldpc_channel_awgn, and msg [batch][k] bytes if msg is not NULL.  Equal to
+ * ldpc_encode of those messages followed by ldpc_channel_awgn, bit for bit.
+ */
+ldpc_status ldpc_generate(ldpc_encoder_t e, int32_t batch, uint64_t seed, uint64_t noise_stream, int64_t first_word,
+                          double sigma2, uint32_t flags, uint8_t *msg, uint8_t *cw, void *llr, hipStream_t stream);
+
+/*
+ * Decision errors against the transmitted codewords (bit and word error counts
+ * behind BER and FER): counts[0] += positions where hard != cw, counts[1] += the
+ * same over message positions, counts[2] += words with any error.  hard, cw
+ * [batch][n] bytes (nonzero = 1); counts: 3 device uint64, 8-byte aligned, added
+ * to (the caller clears them), so several batches accumulate.
+ */
+ldpc_status ldpc_count_errors(ldpc_encoder_t e, const uint8_t *hard, const uint8_t *cw, int32_t batch,
+                              uint64_t *counts, hipStream_t stream);
+
 const char *ldpc_status_string(ldpc_status s);
 const char *ldpc_last_error(void);
 

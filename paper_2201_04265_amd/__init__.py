@@ -7,6 +7,7 @@ missing the calls raise.
 
     g = Graph.from_csr(m, n, indptr, indices)
     hard, post, iters = decode(g, llr, max_iters=50, early_stop=True)
+    enc = Encoder(g); msg, cw, llr = enc.generate(batch, sigma2, seed)   # words made on the device
 """
 from __future__ import annotations
 
@@ -15,3 +16,4 @@ from .graph import Graph  # noqa: F401
 from .decoder import decode, decode_stream, stream_supported, workspace_size  # noqa: F401
 from .multi import STREAM_AUTO, Batch, Plan, Shape, decode_multi, tuned_shape  # noqa: F401
 from .unrolled import UnrolledBP, unrolled_decode  # noqa: F401
+from .encoder import Encoder, channel_awgn  # noqa: F401

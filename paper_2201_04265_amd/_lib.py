@@ -36,6 +36,16 @@ SIGNATURES = {
                               ctypes.c_int),
     "ldpc_unrolled_backward": ([_p, _p, _p, ctypes.c_size_t, _p, _i32, _i32, _p, _p, _p, ctypes.c_size_t, _p],
                                ctypes.c_int),
+    "ldpc_encoder_create": ([_p, ctypes.POINTER(_p)], ctypes.c_int),
+    "ldpc_encoder_destroy": ([_p], ctypes.c_int),
+    "ldpc_encoder_info": ([_p, _pi32, _pi32, _pi32], ctypes.c_int),
+    "ldpc_encoder_positions": ([_p, _p, _p], ctypes.c_int),
+    "ldpc_encode": ([_p, _p, _i32, _p, _p], ctypes.c_int),
+    "ldpc_channel_awgn": ([_p, _i32, _i32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _i64, _u32, _p, _p],
+                          ctypes.c_int),
+    "ldpc_generate": ([_p, _i32, ctypes.c_uint64, ctypes.c_uint64, _i64, ctypes.c_double, _u32, _p, _p, _p, _p],
+                      ctypes.c_int),
+    "ldpc_count_errors": ([_p, _p, _p, _i32, _p, _p], ctypes.c_int),
     "ldpc_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "ldpc_last_error": ([], ctypes.c_char_p),
 }

@@ -29,6 +29,16 @@ struct ldpc_graph_s {
   int lds_limit = 0;                       // LDS bytes per workgroup (unrolled form), 0 = not queried
 };
 
+// Systematic encoder (encode.hip): the host reduction of H and its device map.
+struct ldpc_encoder_s {
+  int32_t n = 0, k = 0, rank = 0;
+  int32_t kw = 0, kwp = 0, rank4 = 0;     // message chunks, row stride of A, rows of A (multiple of 4)
+  std::vector<int32_t> info, pivots;      // message positions (ascending), pivot column of row r
+  int device = 0, lds_limit = 0;
+  uint64_t *d_A = nullptr;                // [rank4][kwp]: bit j of row r = message bit j enters parity r
+  int32_t *d_colmap = nullptr;            // [n]: message index j, or -1 - r for the pivot of row r
+};
+
 // Device view passed to kernels by value.
 struct GraphDev {
   const int32_t *row_ptr;
