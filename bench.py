@@ -187,6 +187,57 @@ def summarize(torch, name, ms, outs, cw, ebn0s, B, code, extra):
     return d
 
 
+GEN_SEED = 220104265
+
+
+def bench_generation(args, torch, P, g, code, ebn0s, B, stream):
+    """Words made on the device (encoder + Philox AWGN channel, one launch per Eb/N0 point), and
+    the whole Eb/N0 sweep on the device: generation, stream decode and error counts."""
+    t0 = time.perf_counter()
+    enc = P.Encoder(g)
+    t_create = time.perf_counter() - t0
+    rate = enc.k / enc.n
+    s2s = [1.0 / (2.0 * rate * 10.0 ** (e / 10.0)) for e in ebn0s]
+    nw = B * len(ebn0s)
+    cw = torch.empty((nw, code.n), dtype=torch.uint8, device="cuda")
+    llr = torch.empty((nw, code.n), dtype=torch.float32, device="cuda")
+
+    def gen():
+        for i, s2 in enumerate(s2s):
+            sl = slice(i * B, (i + 1) * B)
+            enc.generate(B, s2, GEN_SEED, i, 0, out=(None, cw[sl], llr[sl]))
+
+    ms_gen = time_launches(torch, gen, args.steps, args.warmup, stream)
+    outs = (torch.empty((nw, code.n), dtype=torch.uint8, device="cuda"),
+            torch.empty((nw, code.n), dtype=torch.float32, device="cuda"),
+            torch.empty((nw,), dtype=torch.int32, device="cuda"))
+    ws = torch.empty((256,), dtype=torch.uint8, device="cuda")
+    counts = torch.zeros((len(ebn0s), 3), dtype=torch.int64, device="cuda")
+
+    def sweep():
+        counts.zero_()
+        gen()
+        P.decode_stream(g, llr, MAX_ITERS, True, workspace=ws, out=outs)
+        for i in range(len(ebn0s)):
+            sl = slice(i * B, (i + 1) * B)
+            enc.count_errors(outs[0][sl], cw[sl], counts[i])
+
+    ms_sweep = time_launches(torch, sweep, args.steps, args.warmup, stream)
+    c = counts.cpu().tolist()
+    it = outs[2].to(torch.int64)
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
+    bits = nw * code.n
+    return {"encoder_create_s": t_create, "k": enc.k, "rank": enc.rank,
+            "generate_ms": avg(ms_gen), "generate_gbit_s": bits / (avg(ms_gen) * 1e-3) / 1e9,
+            "generate_written_gb_s": bits * 5 / (avg(ms_gen) * 1e-3) / 1e9,
+            "sweep_ms": avg(ms_sweep), "sweep_coded_gbit_s": bits / (avg(ms_sweep) * 1e-3) / 1e9,
+            "note": "seeded Philox draws (seed %d, noise stream = Eb/N0 index): other words than the host-made "
+                    "batch above, same code and channel points" % GEN_SEED,
+            "per_point": [{"ebn0_db": e, "ber_coded": c[i][0] / (B * code.n), "ber_info": c[i][1] / (B * enc.k),
+                           "fer": c[i][2] / B, "mean_iters": float(it[i * B:(i + 1) * B].float().mean().item())}
+                          for i, e in enumerate(ebn0s)]}
+
+
 def bench_c4(args, torch, P):
     """Mixed batch: 4096 words round-robin over six codes at their own Eb/N0, max 50 iterations.
     Per-code plain launches (back to back on one stream) vs one batched persistent launch."""
@@ -406,6 +457,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the library's default shape")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-generation", action="store_true",
+                    help="skip timing the on-device encoder/channel and the on-device sweep")
     ap.add_argument("--paper-cpu-sample", type=int, default=64, help="vectors per code for the oracle thread sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling hardware byte counters)")
@@ -494,6 +547,11 @@ def main():
             r["bitwise_equal_to_plain"] = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain_outs))
         log(f"[bench] stream: {r['ms_per_step']:.1f} ms/step")
 
+    generation = None
+    if not args.no_generation:
+        generation = bench_generation(args, torch, P, g, code, ebn0s, B, stream)
+        log(f"[bench] on-device generation {generation['generate_ms']:.2f} ms, whole sweep {generation['sweep_ms']:.1f} ms")
+
     head = results.get("stream") or results.get("batched") or results["plain"]
     result = {
         "metric": METRIC,
@@ -516,6 +574,8 @@ def main():
         "forms": results,
         "roofline": roofline(head, code, B),
     }
+    if generation is not None:
+        result["device_generation"] = generation
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(code, ebn0s, args.cpu_sample)
