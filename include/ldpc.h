@@ -110,7 +110,7 @@ ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, i
 
 /* ---- stream form: one word per workgroup, state in LDS -------------------- */
 
-/* LDS bytes one word's decoding state needs (4 x edges) and whether it fits
+/* LDS bytes one word's decoding state needs (4 x edges rounded up to 16, + 80) and whether it fits
  * one workgroup of the current device (*supported = 1). */
 ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported);
 

@@ -44,7 +44,14 @@ void free_device(ldpc_graph_s *g) {
   if (g->d_col_idx) (void)hipFree(g->d_col_idx);
   if (g->d_var_ptr) (void)hipFree(g->d_var_ptr);
   if (g->d_var_edges) (void)hipFree(g->d_var_edges);
-  g->d_row_ptr = g->d_col_idx = g->d_var_ptr = g->d_var_edges = nullptr;
+  if (g->d_var_xoff) (void)hipFree(g->d_var_xoff);
+  g->d_row_ptr = g->d_col_idx = g->d_var_ptr = g->d_var_edges = g->d_var_xoff = nullptr;
+}
+
+std::vector<int32_t> byte_offsets(const std::vector<int32_t> &edges) {
+  std::vector<int32_t> o(edges.size());
+  for (size_t i = 0; i < edges.size(); ++i) o[i] = edges[i] * 4;
+  return o;
 }
 
 ldpc_status upload(const std::vector<int32_t> &h, int32_t **d) {
@@ -158,7 +165,8 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, ldpc_format fmt, 
     return hip_error(e, "hipGetDevice");
   }
   if ((st = upload(g->row_ptr, &g->d_row_ptr)) != LDPC_OK || (st = upload(g->col_idx, &g->d_col_idx)) != LDPC_OK ||
-      (st = upload(g->var_ptr, &g->d_var_ptr)) != LDPC_OK || (st = upload(g->var_edges, &g->d_var_edges)) != LDPC_OK) {
+      (st = upload(g->var_ptr, &g->d_var_ptr)) != LDPC_OK || (st = upload(g->var_edges, &g->d_var_edges)) != LDPC_OK ||
+      (st = upload(byte_offsets(g->var_edges), &g->d_var_xoff)) != LDPC_OK) {
     free_device(g);
     delete g;
     return st;

@@ -20,6 +20,7 @@ struct ldpc_graph_s {
   std::vector<int32_t> row_ptr, col_idx, chk_of_edge, var_ptr, var_edges;
   int device = 0;
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_var_ptr = nullptr, *d_var_edges = nullptr;
+  int32_t *d_var_xoff = nullptr;  // var_edges x 4: byte offsets of the edges in a per-edge FP32 array
   // Launch facts of the stream form, filled once on its first call (stream.hip).
   std::mutex stream_mu;
   bool stream_ready = false;
@@ -45,6 +46,7 @@ struct GraphDev {
   const int32_t *col_idx;
   const int32_t *var_ptr;
   const int32_t *var_edges;
+  const int32_t *var_xoff;  // 4 x var_edges
   int32_t m, n, nnz;
   int32_t dc, dv;  // uniform degrees, or 0 when irregular
 };
@@ -55,6 +57,7 @@ inline GraphDev graph_dev(const ldpc_graph_s *g) {
   d.col_idx = g->d_col_idx;
   d.var_ptr = g->d_var_ptr;
   d.var_edges = g->d_var_edges;
+  d.var_xoff = g->d_var_xoff;
   d.m = g->m;
   d.n = g->n;
   d.nnz = (int32_t)g->nnz;

@@ -29,9 +29,12 @@
 
 namespace ldpc {
 
+// X at LDS address 0 (so an edge's byte offset is its LDS address), then the word
+// index and the per-wave syndrome flags.
+__host__ __device__ inline size_t stream_x_bytes(int64_t nnz) { return ((size_t)nnz * 4 + 15) & ~size_t(15); }
 __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
   (void)n;
-  return (size_t)nnz * 4 + 16;
+  return stream_x_bytes(nnz) + 80;
 }
 
 // Workgroup size limit per degree pair: the generic kernels for check degrees above 8
@@ -40,7 +43,7 @@ __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
 template <int DC>
 constexpr int kStreamMaxThreads = DC < -8 ? 512 : 1024;
 
-template <int DC, int DV>
+template <int DC, int DV, bool F64>
 __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     stream_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                          int max_iters, int early_stop, int *counter, uint8_t *__restrict__ hard,
@@ -48,9 +51,10 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
   constexpr int DCM = DC > 0 ? DC : -DC;
   constexpr int DVM = DV > 0 ? DV : -DV;
   extern __shared__ __align__(16) float smem[];
-  __shared__ int s_word;
-  __shared__ int s_unsat[16];  // per wavefront: some check of the word is unsatisfied
   float *X = smem;
+  int *s_misc = (int *)((char *)smem + stream_x_bytes(g.nnz));
+  int &s_word = s_misc[0];
+  int *s_unsat = s_misc + 4;  // [16] per wavefront: some check of the word is unsatisfied
   const int t = threadIdx.x, NT = blockDim.x;
   const int wave = wave_id(), W = NT >> 6;
   const size_t n = (size_t)g.n;
@@ -64,7 +68,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
 
     // ingest: posterior = channel LLRs, first messages X = clamp(R), channel decisions
     for (int v = t; v < g.n; v += NT) {
-      const float x = llr64 ? (float)llr64[base + v] : llr32[base + v];
+      const float x = F64 ? (float)llr64[base + v] : llr32[base + v];
       post[base + v] = x;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
@@ -91,43 +95,59 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       int any_unsat = 0;
       for (int w = 0; w < W; ++w) any_unsat |= s_unsat[w];
       if ((early_stop && !any_unsat) || it == max_iters) break;  // same value in every thread
-      // The global reads of a variable (its edge list, its channel LLR) are issued one
-      // variable ahead, so their latency overlaps the LDS work of the current one.
-      int eidn[DVM], dvn = 0;
-      float rn = 0.0f;
-      auto fetch = [&](int vv) {
-        int p0;
-        var_range<DV>(g, vv, p0, dvn);
-        rn = llr64 ? (float)llr64[base + vv] : llr32[base + vv];
-#pragma unroll
-        for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < dvn) eidn[j] = g.var_edges[p0 + j];
+      // The global reads of a variable (its edge list as LDS byte offsets, its channel
+      // LLR) are issued one variable ahead, so their latency overlaps the work of the
+      // current one.  Two register sets alternate (variables are taken in pairs), so no
+      // loaded value has to be copied out of the way of the next load.
+      const float *__restrict__ lrow32 = llr32 + base;
+      const double *__restrict__ lrow64 = llr64 + base;
+      float *__restrict__ prow = post + base;
+      struct VarIn {
+        int off[DVM];
+        int dv;
+        float r;
       };
-      if (t < g.n) fetch(t);
-      for (int v = t; v < g.n; v += NT) {
-        const int dv = dvn;
-        const float r = rn;
+      // (32-bit byte offsets from uniform bases: the loads take an SGPR base address)
+      auto fetch = [&](int vv, VarIn &f) {
+        int p0;
+        var_range<DV>(g, vv, p0, f.dv);
+        f.r = F64 ? (float)*(const double *)((const char *)lrow64 + (uint32_t)vv * 8u)
+                  : *(const float *)((const char *)lrow32 + (uint32_t)vv * 4u);
+        const uint32_t pb = DV > 0 ? __umul24((uint32_t)vv, 4u * DVM) : (uint32_t)p0 * 4u;
+        const int32_t *__restrict__ ve = (const int32_t *)((const char *)g.var_xoff + pb);
+#pragma unroll
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < f.dv) f.off[j] = ve[j];
+      };
+      auto update = [&](int v, const VarIn &f) {
         float ev[DVM], pre[DVM];
-        int eid[DVM];
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < dv) eid[j] = eidn[j];
-        if (v + NT < g.n) fetch(v + NT);
-#pragma unroll
-        for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < dv) ev[j] = X[eid[j]];
-        float acc = r;
+          if (DV > 0 || j < f.dv) ev[j] = *(const float *)((const char *)X + f.off[j]);
+        float acc = f.r;
 #pragma unroll
         for (int j = 0; j < DVM; ++j) {
-          if (DV > 0 || j < dv) {
+          if (DV > 0 || j < f.dv) {
             pre[j] = acc;
             acc += ev[j];
           }
         }
-        post[base + v] = acc;
+        *(float *)((char *)prow + (uint32_t)v * 4u) = acc;
         const bool z = acc <= 0.0f;
-        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = v2c_store(x, z); });
+        var_exclusive<DV>(pre, ev, f.dv,
+                          [&](int j, float x) { *(float *)((char *)X + f.off[j]) = v2c_store(x, z); });
+      };
+      const int vlast = g.n - 1;
+      VarIn fa, fb;
+      if (t < g.n) fetch(t, fa);
+      int v = t;
+      for (; v + NT < g.n; v += 2 * NT) {
+        fetch(v + NT, fb);
+        update(v, fa);
+        fetch(min(v + 2 * NT, vlast), fa);
+        update(v + NT, fb);
       }
+      if (v < g.n) update(v, fa);
       lds_barrier();  // also orders this iteration's reads of s_unsat before the next writes
       ++it;
     }
@@ -150,10 +170,11 @@ namespace {
 using StreamKernel = void (*)(GraphDev, const float *, const double *, int, int, int, int *, uint8_t *, float *,
                               int32_t *);
 
-StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads) {
+// The kernel for a graph's degrees and the LLR precision (FP32 or FP64 input).
+StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads, bool f64 = false) {
   StreamKernel k = nullptr;
-#define LDPC_PICK(C, V)                    \
-  k = stream_decode_kernel<C, V>;          \
+#define LDPC_PICK(C, V)                                                          \
+  k = f64 ? stream_decode_kernel<C, V, true> : stream_decode_kernel<C, V, false>; \
   max_threads = kStreamMaxThreads<C>
   LDPC_KIND_SWITCH(kernel_kind(g), LDPC_PICK)
 #undef LDPC_PICK
@@ -204,6 +225,9 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
     return LDPC_OK;
   }
   LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int mt = 0;
+  StreamKernel k64 = pick_stream(g, mt, true);
+  LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   for (int i = 0; i < 5; ++i) {
     const int nt = 64 << i;
     int per_cu = 0;
@@ -251,7 +275,7 @@ ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64,
   if (st != LDPC_OK) return st;
   if (batch == 0) return LDPC_OK;
   int max_threads = 1024;
-  StreamKernel k = pick_stream(g, max_threads);
+  StreamKernel k = pick_stream(g, max_threads, llr_f64);
   const size_t lds = stream_lds_bytes(g->nnz, g->n);
   const int nt = threads ? threads : stream_threads(g, max_threads, batch);
   if (nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
