@@ -42,11 +42,11 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "128df3013dc5c77e87100ea92aa4ea7b35193e52", "bytes_per_launch": 88500956258, "read_bytes": 15045516610,
-               "write_bytes": 73455439648},
+               "sha1": "21e20b4bd87525c244e921669270a211665b66a3", "bytes_per_launch": 85802885779, "read_bytes": 15120790131,
+               "write_bytes": 70682095648},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "51ab6042e61a98df6aa1a4be42552e1c9a1e59fe", "bytes_per_launch": 1640417000363, "read_bytes": 960064611211,
-                "write_bytes": 680352389152},
+                "sha1": "36b6e3d89b14d632a56f90c989fcce54eaf7c709", "bytes_per_launch": 1639755123807, "read_bytes": 959628992767,
+                "write_bytes": 680126131040},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
