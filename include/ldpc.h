@@ -129,6 +129,23 @@ ldpc_status ldpc_decode_stream(ldpc_graph_t g, const void *llr, int32_t batch, i
                                uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
                                void *workspace, size_t ws_bytes, int32_t threads, hipStream_t stream);
 
+/* ---- split form: each half-iteration a launch over many workgroups per tile -- */
+
+/*
+ * Same contract and bit-identical outputs as ldpc_decode, for batches with few
+ * 64-word tiles: the plain decoder gives a tile one workgroup for the whole decode,
+ * here each check phase and each variable phase of Algorithm 1 is its own launch
+ * that spreads every tile's checks (variables) over `slices` workgroups (0 = about
+ * 2048 workgroups in all, at least 4 checks or variables per wave); the launch
+ * boundary is the exchange between the phases.  2 (max_iters + 1) + 2 launches are
+ * enqueued; tiles whose words have all stopped return at once.  workspace: device,
+ * >= ldpc_split_workspace_size bytes, 256-byte aligned, no initialisation needed.
+ */
+ldpc_status ldpc_split_workspace_size(ldpc_graph_t g, int32_t batch, size_t *bytes);
+ldpc_status ldpc_decode_split(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
+                              uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
+                              void *workspace, size_t ws_bytes, int32_t slices, hipStream_t stream);
+
 /* ---- batched persistent form --------------------------------------------- */
 
 /* Most codes one batched launch serves. */
@@ -155,15 +172,21 @@ typedef struct {
  * state must fit, see ldpc_stream_lds_bytes, else LDPC_ERR_UNSUPPORTED);
  * LDPC_STREAM_AUTO = every code whose word state fits; 0 = none. */
 #define LDPC_STREAM_AUTO 0xFFFFFFFFu
+/* split_codes: bit q set = code q (if not in stream form) is decoded by the split form
+ * (ldpc_decode_split, its own launches before the persistent one; same outputs bit for
+ * bit); LDPC_SPLIT_AUTO = every such code whose words fill fewer 64-word tiles than
+ * half the GPU's compute units; 0 = none. */
+#define LDPC_SPLIT_AUTO 0xFFFFFFFFu
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];
   int32_t refill;
   uint32_t stream_codes;
+  uint32_t split_codes;
 } ldpc_multi_shape;
 
-/* Shape ldpc_decode_multi would use (automatic slot counts and the stream mask filled
- * in; codes in stream form get 0 slots) and its workspace size. */
+/* Shape ldpc_decode_multi would use (automatic slot counts, the stream and split masks
+ * filled in; codes in stream or split form get 0 slots) and its workspace size. */
 ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                const ldpc_multi_shape *shape, ldpc_multi_shape *resolved, size_t *ws_bytes);
 

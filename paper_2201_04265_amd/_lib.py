@@ -24,6 +24,8 @@ SIGNATURES = {
                            ctypes.c_int),
     "ldpc_stream_lds_bytes": ([_p, _psz, _pi32], ctypes.c_int),
     "ldpc_decode_stream": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _i32, _p], ctypes.c_int),
+    "ldpc_split_workspace_size": ([_p, _i32, _psz], ctypes.c_int),
+    "ldpc_decode_split": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _i32, _p], ctypes.c_int),
     "ldpc_multi_resolve": ([_p, _i32, _p, _p, _p, _psz], ctypes.c_int),
     "ldpc_decode_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
     "ldpc_plan_create_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.c_size_t, _p, ctypes.POINTER(_p)],

@@ -41,7 +41,16 @@ struct StreamCodes {
   ldpc_job job[LDPC_MAX_CODES];
 };
 
-// Enqueues the stream-form decodes (counters at counters + 64 + code), the counter reset
-// and the persistent launch.
+// Codes of a batched decode that run in the split form (host side), each with its
+// workspace region.
+struct SplitCodes {
+  int n = 0;
+  ldpc_graph_s *g[LDPC_MAX_CODES];
+  ldpc_job job[LDPC_MAX_CODES];
+  void *ws[LDPC_MAX_CODES];
+};
+
+// Enqueues the stream-form decodes (counters at counters + 64 + code), the split-form
+// decodes, the counter reset and the persistent launch.
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
-                          hipStream_t stream, const StreamCodes *sc);
+                          hipStream_t stream, const StreamCodes *sc, const SplitCodes *sp);

@@ -240,6 +240,20 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
       return st;
   }
   sh.stream_codes = mask;
+  // codes decoded by the split form: requested ones, or AUTO: few tiles for the GPU
+  uint32_t smask = 0;
+  if (sh.split_codes) {
+    int dev = 0, cus = 0;
+    LDPC_HIP_CHECK(hipGetDevice(&dev));
+    LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int q = 0; q < ncodes; ++q) {
+      if (!((sh.split_codes >> q) & 1u) || ((mask >> q) & 1u) || jobs[q].batch <= 0) continue;
+      const long tiles = (jobs[q].batch + TW - 1) / TW;
+      if (sh.split_codes != LDPC_SPLIT_AUTO || 2 * tiles < cus) smask |= 1u << q;
+    }
+  }
+  sh.split_codes = smask;
+  mask |= smask;  // from here on: codes decoded outside the persistent launch
   for (int q = 0; q < ncodes; ++q)
     if ((mask >> q) & 1u) sh.slots[q] = 0;
   if (sh.waves == 0) {
@@ -292,6 +306,8 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     if (jobs[q].batch == 0) sh.slots[q] = 0;
     bytes += (size_t)sh.slots[q] * tile_bytes(graphs[q]->nnz, graphs[q]->n);
   }
+  for (int q = 0; q < ncodes; ++q)  // then one region per split-form code
+    if ((smask >> q) & 1u) bytes += align256(split_workspace_bytes(graphs[q], jobs[q].batch));
   if (shape_out) *shape_out = sh;
   if (ws_bytes) *ws_bytes = bytes;
   return LDPC_OK;
@@ -331,12 +347,20 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
 }
 
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
-                          hipStream_t stream, const StreamCodes *sc) {
+                          hipStream_t stream, const StreamCodes *sc, const SplitCodes *sp) {
   if (sc) {
     for (int i = 0; i < sc->n; ++i) {
       const ldpc_job &j = sc->job[i];
       ldpc_status st = launch_stream_decode(sc->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
                                             j.posterior, j.iters_used, counters + 64 + sc->code[i], 0, stream);
+      if (st != LDPC_OK) return st;
+    }
+  }
+  if (sp) {
+    for (int i = 0; i < sp->n; ++i) {
+      const ldpc_job &j = sp->job[i];
+      ldpc_status st = launch_split_decode(sp->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
+                                           j.posterior, j.iters_used, sp->ws[i], 0, stream);
       if (st != LDPC_OK) return st;
     }
   }

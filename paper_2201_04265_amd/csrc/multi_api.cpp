@@ -4,6 +4,7 @@
 
 #include "internal.h"
 #include "multi.h"
+#include "tile.h"
 
 extern "C" ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                           const ldpc_multi_shape *shape, ldpc_multi_shape *resolved,
@@ -14,7 +15,7 @@ extern "C" ldpc_status ldpc_multi_resolve(const ldpc_graph_t *graphs, int32_t nc
 static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
                                  const int32_t *const *orders, const ldpc_multi_shape *shape, void *ws,
                                  size_t ws_bytes, MultiArgs *a, int **counters, int *grid, int *waves,
-                                 StreamCodes *sc) {
+                                 StreamCodes *sc, SplitCodes *sp) {
   ldpc_multi_shape sh;
   size_t need = 0;
   ldpc_status st = multi_resolve(graphs, ncodes, jobs, shape, &sh, &need);
@@ -34,6 +35,21 @@ static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, con
     sc->job[sc->n] = j;
     ++sc->n;
   }
+  // split-form regions follow the slot states (the layout of multi_resolve's size)
+  size_t off = 512;
+  for (int q = 0; q < ncodes; ++q) off += (size_t)sh.slots[q] * ldpc::tile_bytes(graphs[q]->nnz, graphs[q]->n);
+  sp->n = 0;
+  for (int q = 0; q < ncodes; ++q) {
+    if (!((sh.split_codes >> q) & 1u)) continue;
+    const ldpc_job &j = jobs[q];
+    if (!j.llr || !j.hard_bits || !j.posterior || !j.iters_used)
+      return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer in job " + std::to_string(q));
+    sp->g[sp->n] = graphs[q];
+    sp->job[sp->n] = j;
+    sp->ws[sp->n] = (char *)ws + off;
+    ++sp->n;
+    off += align256(split_workspace_bytes(graphs[q], j.batch));
+  }
   return multi_args(graphs, ncodes, jobs, orders, sh, ws, a, counters, grid);
 }
 
@@ -43,12 +59,13 @@ extern "C" ldpc_status ldpc_decode_multi(const ldpc_graph_t *graphs, int32_t nco
                                          hipStream_t stream) {
   MultiArgs a{};
   StreamCodes sc;
+  SplitCodes sp;
   int *counters = nullptr;
   int grid = 0, waves = 0;
   ldpc_status st = multi_prepare(graphs, ncodes, jobs, orders, shape, workspace, ws_bytes, &a, &counters, &grid,
-                                 &waves, &sc);
+                                 &waves, &sc, &sp);
   if (st != LDPC_OK) return st;
-  return multi_enqueue(a, counters, grid, waves, early_stop, stream, &sc);
+  return multi_enqueue(a, counters, grid, waves, early_stop, stream, &sc, &sp);
 }
 
 struct ldpc_plan_s {
@@ -65,10 +82,11 @@ extern "C" ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_
   if (!capture_stream) return set_error(LDPC_ERR_INVALID_ARG, "capture needs a non-default stream");
   MultiArgs a{};
   StreamCodes sc;
+  SplitCodes sp;
   int *counters = nullptr;
   int grid = 0, waves = 0;
   ldpc_status st = multi_prepare(graphs, ncodes, jobs, orders, shape, workspace, ws_bytes, &a, &counters, &grid,
-                                 &waves, &sc);
+                                 &waves, &sc, &sp);
   if (st != LDPC_OK) return st;
   ldpc_plan_s *p = new (std::nothrow) ldpc_plan_s();
   if (!p) return set_error(LDPC_ERR_OUT_OF_MEMORY, "plan allocation");
@@ -77,7 +95,7 @@ extern "C" ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_
     delete p;
     return hip_error(e, "hipStreamBeginCapture");
   }
-  st = multi_enqueue(a, counters, grid, waves, early_stop, capture_stream, &sc);
+  st = multi_enqueue(a, counters, grid, waves, early_stop, capture_stream, &sc, &sp);
   e = hipStreamEndCapture(capture_stream, &p->graph);
   if (st != LDPC_OK || e != hipSuccess) {
     if (p->graph) (void)hipGraphDestroy(p->graph);

@@ -84,3 +84,36 @@ def decode_stream(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: b
                                    _ptr(hard), _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(),
                                    int(threads), ctypes.c_void_p(stream_handle(stream))))
     return hard, post, iters
+
+
+def split_workspace_size(graph: Graph, batch: int) -> int:
+    out = ctypes.c_size_t()
+    check("ldpc_split_workspace_size", lib().ldpc_split_workspace_size(graph.handle, int(batch), ctypes.byref(out)))
+    return out.value
+
+
+def decode_split(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = True, slices: int = 0,
+                 workspace: torch.Tensor | None = None, out=None, stream=None):
+    """Split form (each half-iteration one launch over many workgroups per tile); same outputs as decode()."""
+    if not llr.is_cuda or llr.dim() != 2 or llr.shape[1] != graph.n:
+        raise ValueError("llr must be a cuda tensor of shape [B, n]")
+    if llr.dtype not in (torch.float32, torch.float64):
+        raise ValueError("llr must be float32 or float64")
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        hard = torch.empty((B, graph.n), dtype=torch.uint8, device=dev)
+        post = torch.empty((B, graph.n), dtype=torch.float32, device=dev)
+        iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    else:
+        hard, post, iters = out
+    need = split_workspace_size(graph, B)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    flags = LLR_F64 if llr.dtype == torch.float64 else 0
+    check("ldpc_decode_split",
+          lib().ldpc_decode_split(graph.handle, _ptr(llr), B, int(max_iters), int(bool(early_stop)), flags,
+                                  _ptr(hard), _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(),
+                                  int(slices), ctypes.c_void_p(stream_handle(stream))))
+    return hard, post, iters

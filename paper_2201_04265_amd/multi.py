@@ -21,18 +21,20 @@ class Job(ctypes.Structure):
 
 
 STREAM_AUTO = 0xFFFFFFFF  # every code whose word state fits LDS runs in the stream form
+SPLIT_AUTO = 0xFFFFFFFF  # every other code with fewer 64-word tiles than half the compute units: split form
 
 
 class Shape(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32),
-                ("stream_codes", ctypes.c_uint32)]
+                ("stream_codes", ctypes.c_uint32), ("split_codes", ctypes.c_uint32)]
 
     @classmethod
-    def make(cls, waves=0, slots=None, refill=0, stream_codes=0):
+    def make(cls, waves=0, slots=None, refill=0, stream_codes=0, split_codes=0):
         s = cls()
         s.waves = int(waves)
         s.refill = int(refill)
         s.stream_codes = int(stream_codes) & 0xFFFFFFFF
+        s.split_codes = int(split_codes) & 0xFFFFFFFF
         for i, v in enumerate(slots or []):
             s.slots[i] = int(v)
         return s
@@ -41,6 +43,8 @@ class Shape(ctypes.Structure):
         d = {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill}
         if self.stream_codes:
             d["stream_codes"] = [i for i in range(ncodes) if (self.stream_codes >> i) & 1]
+        if self.split_codes:
+            d["split_codes"] = [i for i in range(ncodes) if (self.split_codes >> i) & 1]
         return d
 
 

@@ -163,7 +163,7 @@ def test_c4_stream_codes_equal_per_code_plain(P, c4):
     shape = P.Shape.make(stream_codes=P.STREAM_AUTO)
     resolved, _ = batch.resolve(shape)
     fits = [P.stream_supported(g) for g in graphs]
-    assert fits == [c.nnz * 4 + 16 + 64 <= 160 * 1024 for c in codes]
+    assert fits == [(c.nnz * 4 + 15) // 16 * 16 + 80 + 64 <= 160 * 1024 for c in codes]
     for q in range(len(codes)):
         assert bool((resolved.stream_codes >> q) & 1) == fits[q]
         if fits[q]:
