@@ -35,19 +35,21 @@ constexpr int kSplitWaves = 8;
 
 __host__ __device__ inline size_t split_tiles(int32_t batch) { return ((size_t)batch + TW - 1) / TW; }
 
+// Ingest and egress move 64-variable chunks of a tile through LDS; the slices of a
+// tile take every slices-th chunk.
 template <int DV>
 __global__ void __launch_bounds__(64 * kSplitWaves)
     split_ingest_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
-                        char *ws, SplitCtl *ctl) {
+                        char *ws, SplitCtl *ctl, int slices) {
   __shared__ float stage[TW][TW + 1];
   const int lane = lane_id(), wave = wave_id(), W = blockDim.x >> 6;
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x / slices, s = blockIdx.x - tile * slices;
   const int cw0 = tile * TW;
   const int nvalid = min(TW, B - cw0);
   const TileState st = tile_state_block(ws + (size_t)tile * tile_bytes(g.nnz, g.n), g.nnz, g.n);
-  ingest_tile<DV>(g, llr32, llr64, cw0, nvalid, st, stage, wave, W, lane);
+  ingest_tile<DV>(g, llr32, llr64, cw0, nvalid, st, stage, wave, W, lane, s, slices);
   SplitCtl &c = ctl[tile];
-  if (wave == 0) {
+  if (s == 0 && wave == 0) {
     c.iters[lane] = 0;
     if (lane == 0) {
       c.active[0] = nvalid == TW ? ~0ull : ((1ull << nvalid) - 1ull);
@@ -114,16 +116,16 @@ __global__ void __launch_bounds__(64 * kSplitWaves)
 template <int DV>
 __global__ void __launch_bounds__(64 * kSplitWaves)
     split_egress_kernel(GraphDev g, char *ws, const SplitCtl *ctl, int B, float *__restrict__ post,
-                        uint8_t *__restrict__ hard, int32_t *__restrict__ iters) {
+                        uint8_t *__restrict__ hard, int32_t *__restrict__ iters, int slices) {
   __shared__ float stage[TW][TW + 1];
   const int lane = lane_id(), wave = wave_id(), W = blockDim.x >> 6;
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x / slices, s = blockIdx.x - tile * slices;
   const int cw0 = tile * TW;
   const int nvalid = min(TW, B - cw0);
   const TileState st = tile_state_block(ws + (size_t)tile * tile_bytes(g.nnz, g.n), g.nnz, g.n);
   const int my_iters = ctl[tile].iters[lane];
-  egress_tile<DV>(g, st, my_iters, cw0, nvalid, post, hard, stage, wave, W, lane);
-  if (wave == 0 && lane < nvalid) iters[cw0 + lane] = my_iters;
+  egress_tile<DV>(g, st, my_iters, cw0, nvalid, post, hard, stage, wave, W, lane, s, slices);
+  if (s == 0 && wave == 0 && lane < nvalid) iters[cw0 + lane] = my_iters;
 }
 
 }  // namespace ldpc
@@ -138,10 +140,10 @@ size_t split_workspace_bytes(const ldpc_graph_s *g, int32_t batch) {
 namespace {
 
 struct SplitKernels {
-  void (*ingest)(GraphDev, const float *, const double *, int, char *, SplitCtl *);
+  void (*ingest)(GraphDev, const float *, const double *, int, char *, SplitCtl *, int);
   void (*check)(GraphDev, char *, SplitCtl *, int, int);
   void (*var)(GraphDev, char *, SplitCtl *, int, int, int, int);
-  void (*egress)(GraphDev, char *, const SplitCtl *, int, float *, uint8_t *, int32_t *);
+  void (*egress)(GraphDev, char *, const SplitCtl *, int, float *, uint8_t *, int32_t *, int);
 };
 
 SplitKernels pick_split(const ldpc_graph_s *g) {
@@ -180,7 +182,9 @@ ldpc_status launch_split_decode(const ldpc_graph_s *g, const void *llr, bool llr
   const float *l32 = llr_f64 ? nullptr : (const float *)llr;
   const double *l64 = llr_f64 ? (const double *)llr : nullptr;
   const dim3 block(64 * kSplitWaves);
-  hipLaunchKernelGGL(k.ingest, dim3((unsigned)tiles), block, 0, stream, d, l32, l64, (int)batch, states, ctl);
+  const int cslices = std::min(slices, (g->n + TW - 1) / TW);  // ingest / egress: at most one chunk each
+  hipLaunchKernelGGL(k.ingest, dim3((unsigned)(tiles * cslices)), block, 0, stream, d, l32, l64, (int)batch, states,
+                     ctl, cslices);
   LDPC_HIP_CHECK(hipGetLastError());
   const dim3 grid((unsigned)(tiles * slices));
   for (int it = 0; it <= max_iters; ++it) {
@@ -189,8 +193,8 @@ ldpc_status launch_split_decode(const ldpc_graph_s *g, const void *llr, bool llr
                        slices);
   }
   LDPC_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k.egress, dim3((unsigned)tiles), block, 0, stream, d, states, (const SplitCtl *)ctl,
-                     (int)batch, post, hard, iters);
+  hipLaunchKernelGGL(k.egress, dim3((unsigned)(tiles * cslices)), block, 0, stream, d, states,
+                     (const SplitCtl *)ctl, (int)batch, post, hard, iters, cslices);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;
 }

@@ -59,9 +59,10 @@ __device__ __forceinline__ void check_range(const GraphDev &g, int c, int &e0, i
 template <int DV>
 __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__restrict__ llr32,
                                             const double *__restrict__ llr64, int cw0, int nvalid, TileState st,
-                                            float (*stage)[TW + 1], int wave, int W, int lane) {
+                                            float (*stage)[TW + 1], int wave, int W, int lane, int chunk0 = 0,
+                                            int chunk_step = 1) {
   const int n = g.n;
-  for (int v0 = 0; v0 < n; v0 += TW) {
+  for (int v0 = chunk0 * TW; v0 < n; v0 += chunk_step * TW) {  // 64-variable chunks
     for (int r = wave; r < TW; r += W) {
       float x = 0.0f;
       const int v = v0 + lane;
@@ -89,11 +90,12 @@ __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__re
 template <int DV>
 __device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int my_iters, int cw0, int nvalid,
                                             float *__restrict__ post, uint8_t *__restrict__ hard,
-                                            float (*stage)[TW + 1], int wave, int W, int lane) {
+                                            float (*stage)[TW + 1], int wave, int W, int lane, int chunk0 = 0,
+                                            int chunk_step = 1) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
   const int n = g.n;
   const float *Eb = (my_iters & 1) ? st.E1 : st.E0;
-  for (int v0 = 0; v0 < n; v0 += TW) {
+  for (int v0 = chunk0 * TW; v0 < n; v0 += chunk_step * TW) {  // 64-variable chunks
     for (int q = wave; q < TW && v0 + q < n; q += W) {
       const int v = v0 + q;
       int p0, dv;
