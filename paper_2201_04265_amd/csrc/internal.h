@@ -20,7 +20,7 @@ struct ldpc_graph_s {
   std::vector<int32_t> row_ptr, col_idx, chk_of_edge, var_ptr, var_edges;
   int device = 0;
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_var_ptr = nullptr, *d_var_edges = nullptr;
-  int32_t *d_var_xoff = nullptr;  // var_edges x 4: byte offsets of the edges in a per-edge FP32 array
+  int32_t *d_var_xoff = nullptr;  // stream form: LDS byte offsets of the edges (var_edges order)
   // Launch facts of the stream form, filled once on its first call (stream.hip).
   std::mutex stream_mu;
   bool stream_ready = false;
@@ -46,7 +46,7 @@ struct GraphDev {
   const int32_t *col_idx;
   const int32_t *var_ptr;
   const int32_t *var_edges;
-  const int32_t *var_xoff;  // 4 x var_edges
+  const int32_t *var_xoff;  // stream form: LDS byte offsets of the edges (var_edges order)
   int32_t m, n, nnz;
   int32_t dc, dv;  // uniform degrees, or 0 when irregular
 };

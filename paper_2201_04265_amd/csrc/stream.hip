@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
       const float mx = v2c_store(x, x <= 0.0f);
-      for (int j = 0; j < dv; ++j) X[g.var_edges[p0 + j]] = mx;
+      for (int j = 0; j < dv; ++j) *(float *)((char *)X + g.var_xoff[p0 + j]) = mx;
     }
     lds_barrier();
 
@@ -209,8 +209,85 @@ int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
   return best_nt;
 }
 
+// Where the check rows sit in LDS.  For a fixed check degree any order of the rows
+// gives the same results (each check reads and writes only its own row), so the rows
+// are placed in the order that keeps the LDS banks of the 64 variables a wavefront
+// updates together as distinct as possible: swaps of two rows' places are kept when
+// they do not raise the summed worst-bank load of the affected (64-variable block,
+// edge rank) groups (a seeded local search, 100 swaps per check).  Returns each
+// variable edge's LDS byte offset in var_edges order.
+std::vector<int32_t> stream_edge_offsets(const ldpc_graph_s *g) {
+  const size_t E = (size_t)g->nnz;
+  std::vector<int32_t> off(E);
+  const bool fixed = g->dc_min == g->dc_max && g->m >= 2;
+  if (!fixed) {
+    for (size_t p = 0; p < E; ++p) off[p] = g->var_edges[p] * 4;
+    return off;
+  }
+  constexpr int kBanks = 64;
+  const int DC = g->dc_max, m = g->m, n = g->n, DV = std::max(1, g->dv_max);
+  // group of edge e: (variable block of 64, rank of e among its variable's edges)
+  std::vector<int32_t> grp(E);
+  for (int v = 0; v < n; ++v)
+    for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p) grp[g->var_edges[p]] = (v >> 6) * DV + (p - g->var_ptr[v]);
+  const size_t ngroups = (size_t)((n + 63) >> 6) * DV;
+  std::vector<uint16_t> cnt(ngroups * kBanks, 0);
+  std::vector<int32_t> slot(m);
+  for (int c = 0; c < m; ++c) slot[c] = c;
+  auto add = [&](int c, int s, int d) {
+    for (int j = 0; j < DC; ++j) cnt[(size_t)grp[(size_t)c * DC + j] * kBanks + (s * DC + j) % kBanks] += d;
+  };
+  for (int c = 0; c < m; ++c) add(c, c, 1);
+  auto worst = [&](int32_t gid) {
+    const uint16_t *r = &cnt[(size_t)gid * kBanks];
+    int w = 0;
+    for (int b = 0; b < kBanks; ++b) w = std::max<int>(w, r[b]);
+    return w;
+  };
+  std::vector<int32_t> gs;
+  gs.reserve(2 * DC);
+  uint64_t x = 0x9E3779B97F4A7C15ull;  // xorshift64*, fixed seed: the same layout every time
+  auto rnd = [&]() {
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return (x * 0x2545F4914F6CDD1Dull) >> 33;
+  };
+  const long swaps = 100L * m;
+  for (long it = 0; it < swaps; ++it) {
+    const int a = (int)(rnd() % (uint64_t)m), b = (int)(rnd() % (uint64_t)m);
+    if (a == b) continue;
+    gs.clear();
+    for (int j = 0; j < DC; ++j)
+      for (int c : {a, b}) {
+        const int32_t gid = grp[(size_t)c * DC + j];
+        if (std::find(gs.begin(), gs.end(), gid) == gs.end()) gs.push_back(gid);
+      }
+    long before = 0, after = 0;
+    for (int32_t gid : gs) before += worst(gid);
+    add(a, slot[a], -1);
+    add(b, slot[b], -1);
+    add(a, slot[b], 1);
+    add(b, slot[a], 1);
+    for (int32_t gid : gs) after += worst(gid);
+    if (after <= before) {
+      std::swap(slot[a], slot[b]);
+    } else {
+      add(a, slot[b], -1);
+      add(b, slot[a], -1);
+      add(a, slot[a], 1);
+      add(b, slot[b], 1);
+    }
+  }
+  for (size_t p = 0; p < E; ++p) {
+    const int32_t e = g->var_edges[p];
+    off[p] = (slot[e / DC] * DC + e % DC) * 4;
+  }
+  return off;
+}
+
 // Device facts the launch needs (the LDS opt-in of the kernel, compute units, resident
-// workgroups per size), queried once per graph instead of on every call.
+// workgroups per size) and the LDS placement of the rows, prepared once per graph.
 ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, size_t lds) {
   std::lock_guard<std::mutex> lock(g->stream_mu);
   if (g->stream_ready) return LDPC_OK;
@@ -219,6 +296,10 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
   LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   LDPC_HIP_CHECK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   g->stream_lds_limit = lim;
+  if (lds + 64 <= (size_t)lim) {
+    const std::vector<int32_t> off = stream_edge_offsets(g);
+    LDPC_HIP_CHECK(hipMemcpy(g->d_var_xoff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   if (lds + 64 > (size_t)lim) {  // cannot run; remember the limit only
     g->stream_cus = cus;
     g->stream_ready = true;
