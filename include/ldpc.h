@@ -118,10 +118,9 @@ ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *suppor
  * Same contract and bit-identical outputs as ldpc_decode, computed by the stream
  * form (Sec. III-B's spreading of one word over many workers, here the threads of
  * one workgroup with every message in LDS).  Persistent workgroups take words from
- * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024, up to 512
- * for codes outside the fixed degree pairs with a check degree above 8; 0 = the size
- * up to 512 that keeps the most threads resident); a larger value returns
- * LDPC_ERR_INVALID_ARG.  The channel LLRs are read again in every iteration.  workspace: >= 256 device
+ * an atomic counter.  threads: workgroup size (multiple of 64 up to 1024; 0 = the
+ * size up to 512 that keeps the most threads resident, or 1024 when one 512-thread
+ * workgroup fills a compute unit's LDS); another value returns LDPC_ERR_INVALID_ARG.  The channel LLRs are read again in every iteration.  workspace: >= 256 device
  * bytes (the counter).  Returns LDPC_ERR_UNSUPPORTED when the word state exceeds the
  * LDS of one workgroup.
  */

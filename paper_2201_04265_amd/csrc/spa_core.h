@@ -75,9 +75,10 @@ __device__ __forceinline__ float v2c_store(float x, bool z) {
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 // AUX: also returns, per edge, q_j = e^-|M_j| in aq and r_j = e^|E_j| (the ratio s / d
 // whose logarithm is the output magnitude) in ar, for the adjoint.
-template <int DC, bool STORED = false, bool AUX = false>
-__device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *eout, float *aq = nullptr,
-                                               float *ar = nullptr) {
+// emit(j, E_j) receives the outputs, last edge first, after every input has been read.
+template <int DC, bool STORED = false, bool AUX = false, class Emit>
+__device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emit emit, float *aq = nullptr,
+                                                    float *ar = nullptr) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   // qs[j] = q_j, and the sign of M_j: for degrees up to 16 the message's bit pattern is
@@ -150,7 +151,7 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
         ar[j] = fmaxf(ratio, 1.0f);
       }
       const uint32_t sgn = (sx ^ (KEEP_BITS ? mb[KEEP_BITS ? j : 0] : __float_as_uint(qs[j]))) & 0x80000000u;
-      eout[j] = __uint_as_float(sgn | __float_as_uint(mag));
+      emit(j, __uint_as_float(sgn | __float_as_uint(mag)));
       const float q = fabsf(qs[j]);
       if (top) {
         d = q;
@@ -160,6 +161,80 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
         s = fmaf(d, q, s);
         d = dn;
       }
+    }
+  }
+  return sx;
+}
+
+// The same with the outputs in an array.
+template <int DC, bool STORED = false, bool AUX = false>
+__device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *eout, float *aq = nullptr,
+                                               float *ar = nullptr) {
+  return check_core_emit<DC, STORED, AUX>(mv, dc, [&](int j, float v) { eout[j] = v; }, aq, ar);
+}
+
+// check_core for a runtime degree (DC < 0) on stored messages, in place on the check's
+// own LDS row: the row holds the inputs, then (while the prefix pairs are formed) the
+// second halves of the prefix pairs, then the outputs.  Each row entry is read back
+// before it is overwritten by the same thread.  The arithmetic and its order are
+// those of check_core<DC, true>, so the outputs are the same bit for bit; the row
+// stands in for one of the three register arrays of -DC values.
+template <int DC>
+__device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
+  static_assert(DC < 0, "runtime degrees only");
+  constexpr int DMAX = -DC;
+  float qs[DMAX], pd[DMAX];
+  uint32_t sx = 0;
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) {
+    if (j < dc) {
+      const uint32_t b = __float_as_uint(row[j]);
+      sx ^= b;
+      const float q = __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown));
+      qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
+    }
+  }
+  float d = 0.0f, s = 1.0f;
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) {
+    if (j < dc) {
+      pd[j] = d;
+      row[j] = s;
+      const float q = fabsf(qs[j]);
+      if (j == 0) {
+        d = q;
+        s = 1.0f;
+      } else {
+        const float dn = fmaf(s, q, d);
+        s = fmaf(d, q, s);
+        d = dn;
+      }
+    }
+  }
+  d = 0.0f;
+  s = 1.0f;
+#pragma unroll
+  for (int j = DMAX - 1; j >= 0; --j) {
+    if (j < dc) {
+      float od, os;
+      if (j == 0) {
+        od = d;
+        os = s;
+      } else {
+        // after one element the second half is exactly 1: written as the literal, as it
+        // is a constant in check_core, so that the compiler forms the same operations
+        const float psj = j == 1 ? 1.0f : row[j];
+        od = fmaf(psj, d, pd[j] * s);
+        os = fmaf(pd[j], d, psj * s);
+      }
+      const float ratio = os * __builtin_amdgcn_rcpf(od);
+      const float mag = fabsf(__builtin_amdgcn_logf(ratio)) * kLn2;
+      const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
+      row[j] = __uint_as_float(sgn | __float_as_uint(mag));
+      const float q = fabsf(qs[j]);
+      const float dn = fmaf(s, q, d);
+      s = fmaf(d, q, s);
+      d = dn;
     }
   }
   return sx;

@@ -37,11 +37,11 @@ __host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
   return stream_x_bytes(nnz) + 80;
 }
 
-// Workgroup size limit per degree pair: the generic kernels for check degrees above 8
-// hold up to 32 messages per thread and would spill under the 128-VGPR budget of a
-// 1024-thread workgroup, so they are built for at most 512 threads (256 VGPRs).
+// Workgroup size limit per degree pair: every kernel fits the 128-VGPR budget of a
+// 1024-thread workgroup (the runtime-degree kernels keep half of their prefix pairs in
+// the check's LDS row, see check_core_row).
 template <int DC>
-constexpr int kStreamMaxThreads = DC < -8 ? 512 : 1024;
+constexpr int kStreamMaxThreads = 1024;
 
 template <int DC, int DV, bool F64>
 __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
@@ -83,10 +83,15 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       for (int c = t; c < g.m; c += NT) {
         int e0, dc;
         check_range<DC>(g, c, e0, dc);
-        float mv[DCM], ev[DCM];
-        lds_row_load<DC>(X + e0, dc, mv);
-        const uint32_t sx = check_core<DC, true>(mv, dc, ev);
-        lds_row_store<DC>(X + e0, dc, ev);
+        uint32_t sx;
+        if constexpr (DC > 0) {  // whole rows move with 8- or 16-byte LDS accesses
+          float mv[DCM], ev[DCM];
+          lds_row_load<DC>(X + e0, dc, mv);
+          sx = check_core<DC, true>(mv, dc, ev);
+          lds_row_store<DC>(X + e0, dc, ev);
+        } else {  // in place on the row, which also holds half of the prefix pairs
+          sx = check_core_row<DC>(X + e0, dc);
+        }
         unsat |= syndrome_bit(sx);
       }
       const unsigned long long b = __ballot(unsat);
@@ -187,7 +192,9 @@ StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads, bool f64 = fal
 // than the resident capacity is counted at its own size.  Above 512 threads the cost
 // of bringing every wave to each of the two barriers per iteration outweighs the
 // shorter phases: 512 beat 1024 on (3,6) n=4096 both in throughput (by ~5 %) and for
-// a single word, and on the n=1032 Table I codes.
+// a single word, and on the n=1032 Table I codes.  The exception is a word state so
+// large that one workgroup fills a compute unit's LDS: then 8 waves cannot hide the
+// LDS and memory latencies and 1024 threads (16 waves) are taken when they fit.
 constexpr int kStreamDefaultMaxThreads = 512;
 
 int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
@@ -206,6 +213,9 @@ int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
       best_nt = nt;
     }
   }
+  if (max_threads >= 1024 && top >= kStreamDefaultMaxThreads && big > kStreamDefaultMaxThreads &&
+      g->stream_per_cu[4] >= 1 && g->stream_per_cu[3] <= 1)
+    best_nt = 1024;
   return best_nt;
 }
 

@@ -110,8 +110,10 @@ def test_too_large_is_unsupported(P):
     assert e.value.status == -5
 
 
-def test_thread_limit_of_generic_high_degree_codes(P):
-    """Codes outside the fixed degree pairs with a check degree above 8 run at most 512 threads."""
+def test_generic_high_degree_codes_every_workgroup_size(P):
+    """Codes outside the fixed degree pairs with check degree 20 (runtime-degree kernel, prefix
+    pairs half in the LDS row): 1024- and 512-thread workgroups, both equal to the plain decoder;
+    sizes beyond 1024 are refused."""
     rng = np.random.default_rng(77)
     n, m = 300, 40
     chk, var = [], []
@@ -123,7 +125,8 @@ def test_thread_limit_of_generic_high_degree_codes(P):
     g = P.Graph.from_code(code)
     x = torch.from_numpy(rng.normal(2.0, 2.0, size=(9, n)).astype(np.float32)).cuda()
     with pytest.raises(P.LdpcError) as e:
-        P.decode_stream(g, x, 5, threads=1024)
+        P.decode_stream(g, x, 5, threads=1088)
     assert e.value.status == -1
-    a, b = both(P, g, x.cpu().numpy(), 12, True, 512)
-    same(a, b)
+    for nt in (1024, 512):
+        a, b = both(P, g, x.cpu().numpy(), 12, True, nt)
+        same(a, b)
