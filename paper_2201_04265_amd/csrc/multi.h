@@ -50,7 +50,19 @@ struct SplitCodes {
   void *ws[LDPC_MAX_CODES];
 };
 
-// Enqueues the stream-form decodes (counters at counters + 64 + code), the split-form
-// decodes, the counter reset and the persistent launch.
+// A second stream (default priority) and two events: the split-form decodes of a
+// batched call run on it beside the call's other launches (they touch disjoint outputs
+// and workspace regions), forked from and joined back into the caller's stream.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+// The calling thread's side stream for the current device (created on first use; NULL
+// if none is available).
+ldpc_status multi_side_stream(SideStream **out);
+
+// Enqueues the split-form decodes (on the side stream, forked from and joined back into
+// `stream`, when there are other launches to overlap), the stream-form decodes
+// (counters at counters + 64 + code), the counter reset and the persistent launch.
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
                           hipStream_t stream, const StreamCodes *sc, const SplitCodes *sp);

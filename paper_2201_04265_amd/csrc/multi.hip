@@ -346,8 +346,50 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
   return LDPC_OK;
 }
 
+namespace {
+constexpr int kSideDevices = 64;
+}  // namespace
+
+// Side streams are created on first use, one per device and host thread, and kept for
+// the process.
+ldpc_status multi_side_stream(SideStream **out) {
+  thread_local SideStream cache[kSideDevices];
+  *out = nullptr;
+  int dev = 0;
+  LDPC_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kSideDevices) return LDPC_OK;  // no side stream: everything on the caller's
+  SideStream &c = cache[dev];
+  if (!c.s) {
+    LDPC_HIP_CHECK(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+    LDPC_HIP_CHECK(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+    LDPC_HIP_CHECK(hipEventCreateWithFlags(&c.join, hipEventDisableTiming));
+  }
+  *out = &c;
+  return LDPC_OK;
+}
+
 ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves, int early_stop,
                           hipStream_t stream, const StreamCodes *sc, const SplitCodes *sp) {
+  SideStream *side = nullptr;
+  if (sp && sp->n > 0 && ((sc && sc->n > 0) || grid > 0)) {
+    ldpc_status st = multi_side_stream(&side);
+    if (st != LDPC_OK) return st;
+  }
+  hipStream_t split_stream = stream;
+  if (side) {
+    LDPC_HIP_CHECK(hipEventRecord(side->fork, stream));
+    LDPC_HIP_CHECK(hipStreamWaitEvent(side->s, side->fork, 0));
+    split_stream = side->s;
+  }
+  if (sp) {
+    for (int i = 0; i < sp->n; ++i) {
+      const ldpc_job &j = sp->job[i];
+      ldpc_status st = launch_split_decode(sp->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
+                                           j.posterior, j.iters_used, sp->ws[i], 0, split_stream);
+      if (st != LDPC_OK) return st;
+    }
+  }
+  if (side) LDPC_HIP_CHECK(hipEventRecord(side->join, side->s));
   if (sc) {
     for (int i = 0; i < sc->n; ++i) {
       const ldpc_job &j = sc->job[i];
@@ -356,19 +398,13 @@ ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves
       if (st != LDPC_OK) return st;
     }
   }
-  if (sp) {
-    for (int i = 0; i < sp->n; ++i) {
-      const ldpc_job &j = sp->job[i];
-      ldpc_status st = launch_split_decode(sp->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
-                                           j.posterior, j.iters_used, sp->ws[i], 0, stream);
-      if (st != LDPC_OK) return st;
-    }
-  }
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counters, a.njobs);
   LDPC_HIP_CHECK(hipGetLastError());
-  if (grid == 0) return LDPC_OK;
-  hipLaunchKernelGGL(multi_kernel_for(a), dim3(grid), dim3(64 * waves), 0, stream, a, counters,
-                     (int)(early_stop != 0));
-  LDPC_HIP_CHECK(hipGetLastError());
+  if (grid > 0) {
+    hipLaunchKernelGGL(multi_kernel_for(a), dim3(grid), dim3(64 * waves), 0, stream, a, counters,
+                       (int)(early_stop != 0));
+    LDPC_HIP_CHECK(hipGetLastError());
+  }
+  if (side) LDPC_HIP_CHECK(hipStreamWaitEvent(stream, side->join, 0));
   return LDPC_OK;
 }

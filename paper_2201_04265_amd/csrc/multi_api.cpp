@@ -88,6 +88,11 @@ extern "C" ldpc_status ldpc_plan_create_multi(const ldpc_graph_t *graphs, int32_
   ldpc_status st = multi_prepare(graphs, ncodes, jobs, orders, shape, workspace, ws_bytes, &a, &counters, &grid,
                                  &waves, &sc, &sp);
   if (st != LDPC_OK) return st;
+  if (sp.n > 0) {  // create the side stream before the capture begins
+    SideStream *side = nullptr;
+    st = multi_side_stream(&side);
+    if (st != LDPC_OK) return st;
+  }
   ldpc_plan_s *p = new (std::nothrow) ldpc_plan_s();
   if (!p) return set_error(LDPC_ERR_OUT_OF_MEMORY, "plan allocation");
   hipError_t e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal);
