@@ -79,7 +79,11 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
 
     int it = 0;
     for (;;) {
-      int unsat = 0;
+      uint32_t sxs = 0;  // OR of the checks' parities: bit 30 set iff one is unsatisfied
+      // two low-degree checks in flight per thread (more independent work per wave; the
+      // higher degrees would lose resident waves to the registers it takes)
+      constexpr int kCheckUnroll = DC > 0 && DC <= 8 ? 2 : 1;
+#pragma unroll kCheckUnroll
       for (int c = t; c < g.m; c += NT) {
         int e0, dc;
         check_range<DC>(g, c, e0, dc);
@@ -92,9 +96,9 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         } else {  // in place on the row, which also holds half of the prefix pairs
           sx = check_core_row<DC>(X + e0, dc);
         }
-        unsat |= syndrome_bit(sx);
+        sxs |= sx;
       }
-      const unsigned long long b = __ballot(unsat);
+      const unsigned long long b = __ballot(syndrome_bit(sxs));
       if ((t & 63) == 0) s_unsat[wave] = b != 0ull;
       lds_barrier();
       int any_unsat = 0;
