@@ -51,11 +51,10 @@ COUNTER_TRAFFIC = {
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
 # VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 178 VALU instructions per pair of degree-6 checks and 50 per pair of degree-3 variables
+# code: 178 VALU instructions per pair of degree-6 checks and 44 per pair of degree-3 variables
 # (both loops take two at a time), loop control included; one wave64 instruction = 64
-# lane-slots.  The counters show SQ_INSTS_VALU x 4 cycles close to all of the SIMD cycles of the
-# launch, so the exp2 / log2 / rcp among them add no issue cycles.
-STREAM_VALU_SLOTS_PER_EDGE = 89 / 6.0 + 25 / 3.0
+# lane-slots.  The exp2 / log2 / rcp among them add no issue cycles of their own.
+STREAM_VALU_SLOTS_PER_EDGE = 89 / 6.0 + 22 / 3.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 

@@ -128,11 +128,14 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         for (int j = 0; j < DVM; ++j)
           if (DV > 0 || j < f.dv) f.off[j] = ve[j];
       };
+      // X is the kernel's only LDS, so it starts at LDS address 0 (checked on the host)
+      // and an edge's byte offset is its LDS address.
+      auto xat = [](int off) { return (__attribute__((address_space(3))) float *)(size_t)off; };
       auto update = [&](int v, const VarIn &f) {
         float ev[DVM], pre[DVM];
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < f.dv) ev[j] = *(const float *)((const char *)X + f.off[j]);
+          if (DV > 0 || j < f.dv) ev[j] = *xat(f.off[j]);
         float acc = f.r;
 #pragma unroll
         for (int j = 0; j < DVM; ++j) {
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         *(float *)((char *)prow + (uint32_t)v * 4u) = acc;
         const bool z = acc <= 0.0f;
         var_exclusive<DV>(pre, ev, f.dv,
-                          [&](int j, float x) { *(float *)((char *)X + f.off[j]) = v2c_store(x, z); });
+                          [&](int j, float x) { *xat(f.off[j]) = v2c_store(x, z); });
       };
       const int vlast = g.n - 1;
       VarIn fa, fb;
@@ -320,9 +323,16 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
     return LDPC_OK;
   }
   LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipFuncAttributes fa{};
+  LDPC_HIP_CHECK(hipFuncGetAttributes(&fa, (const void *)k));
+  if (fa.sharedSizeBytes != 0)  // the kernel addresses its messages from LDS address 0
+    return set_error(LDPC_ERR_DEVICE, "stream kernel has static LDS; its message array would not start at 0");
   int mt = 0;
   StreamKernel k64 = pick_stream(g, mt, true);
   LDPC_HIP_CHECK(hipFuncSetAttribute((const void *)k64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  LDPC_HIP_CHECK(hipFuncGetAttributes(&fa, (const void *)k64));
+  if (fa.sharedSizeBytes != 0)
+    return set_error(LDPC_ERR_DEVICE, "stream kernel has static LDS; its message array would not start at 0");
   for (int i = 0; i < 5; ++i) {
     const int nt = 64 << i;
     int per_cu = 0;
