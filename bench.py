@@ -398,15 +398,21 @@ def bench_paper(args, torch, P):
                              args.warmup, stream)
         ms_1 = time_launches(torch, lambda: P.decode_stream(g, x[:1], T, False, workspace=ws1, out=s1),
                              max(args.steps, 20), args.warmup, stream)
+        wsp = torch.empty(P.split_workspace_size(g, nvec), dtype=torch.uint8, device="cuda")
+        sp_o = outs(nvec, c.n)
+        ms_sp = time_launches(torch, lambda: P.decode_split(g, x, T, False, workspace=wsp, out=sp_o), args.steps,
+                              args.warmup, stream)
         same = all(bool(torch.equal(a, b)) for a, b in zip(po, so))
+        same &= all(bool(torch.equal(a, b)) for a, b in zip(po, sp_o))
         errs = so[0] != cw
         per_code.append({"code": c.name, "m": c.m, "n": c.n, "edges": c.nnz, "dv": c.nnz // c.n,
                          "rate": W.rate(W.PAPER["codes"][i]),
                          "plain_us_per_vector": avg(ms_p) * 1e3 / nvec,
                          "stream_us_per_vector": avg(ms_s) * 1e3 / nvec,
+                         "split_us_per_vector": avg(ms_sp) * 1e3 / nvec,
                          "stream_single_vector_us": avg(ms_1) * 1e3,
                          "stream_edge_updates_per_s": nvec * T * c.nnz / (avg(ms_s) * 1e-3),
-                         "stream_equal_to_plain": same, "ber_coded": float(errs.float().mean().item()),
+                         "stream_and_split_equal_to_plain": same, "ber_coded": float(errs.float().mean().item()),
                          "fer": float(errs.any(dim=1).float().mean().item())})
         log(f"[bench] {c.name}: plain {avg(ms_p):.3f} ms, stream {avg(ms_s):.3f} ms, one vector {avg(ms_1):.3f} ms")
 
