@@ -527,7 +527,7 @@ def main():
         ms = time_launches(torch, lambda: P.decode(g, llr, MAX_ITERS, True, workspace=ws, out=outs),
                            args.steps, args.warmup, stream)
         results["plain"] = summarize(torch, "plain", ms, outs, cw, ebn0s, B, code,
-                                     {"kernel": "plain_decode_kernel<6,3>", "waves": 8})
+                                     {"kernel": "plain_decode_kernel<6,3>", "waves": 16})
         log(f"[bench] plain: {results['plain']['ms_per_step']:.1f} ms/step")
         plain_outs = outs
         del ws

@@ -103,7 +103,8 @@ ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t 
                         uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used, void *workspace,
                         size_t ws_bytes, hipStream_t stream);
 
-/* Decode with an explicit launch shape: waves per workgroup (1..16). Same contract as ldpc_decode. */
+/* Decode with an explicit launch shape: waves per workgroup (1..16; ldpc_decode uses 16).
+ * Same contract as ldpc_decode. */
 ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
                                uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
                                void *workspace, size_t ws_bytes, int32_t waves, hipStream_t stream);

@@ -227,8 +227,10 @@ static ldpc_status decode_common(ldpc_graph_t g, const void *llr, int32_t batch,
 extern "C" ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
                                    int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
                                    int32_t *iters_used, void *workspace, size_t ws_bytes, hipStream_t stream) {
+  // 16 waves per tile: more loads in flight per compute unit (against 8 waves: 1.5x on the
+  // n=11264 quasi-cyclic code, 1.4x on n=1032 Table I batches, 1.06x on (3,6) n=4096)
   return decode_common(g, llr, batch, max_iters, early_stop, flags, hard_bits, posterior, iters_used, workspace,
-                       ws_bytes, 8, stream);
+                       ws_bytes, 16, stream);
 }
 
 extern "C" ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
