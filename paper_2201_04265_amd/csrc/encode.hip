@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void awgn_kernel(const uint8_t *__restrict__ c
 __global__ __launch_bounds__(256) void count_errors_kernel(const uint8_t *__restrict__ hard,
                                                            const uint8_t *__restrict__ cw,
                                                            const int32_t *__restrict__ colmap, int32_t n,
-                                                           int32_t batch, unsigned long long *counts) {
+                                                           int32_t batch, bool vec, unsigned long long *counts) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -273,10 +273,24 @@ __global__ __launch_bounds__(256) void count_errors_kernel(const uint8_t *__rest
   for (int64_t w = wave; w < batch; w += nwaves) {
     const uint8_t *h = hard + (size_t)w * n, *c = cw + (size_t)w * n;
     uint32_t a = 0, b = 0;
-    for (int v = lane; v < n; v += 64) {
-      const uint32_t d = (h[v] != 0) != (c[v] != 0);
-      a += d;
-      b += d & (uint32_t)(colmap[v] >= 0);
+    if (vec) {  // rows 4-byte aligned: four positions per lane and load
+      for (int v = 4 * lane; v < n; v += 256) {
+        const uint32_t hh = *(const uint32_t *)(h + v), cc = *(const uint32_t *)(c + v);
+        const int4 cm = *(const int4 *)(colmap + v);
+        const int32_t cms[4] = {cm.x, cm.y, cm.z, cm.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t d = (((hh >> (8 * i)) & 0xffu) != 0) != (((cc >> (8 * i)) & 0xffu) != 0);
+          a += d;
+          b += d & (uint32_t)(cms[i] >= 0);
+        }
+      }
+    } else {
+      for (int v = lane; v < n; v += 64) {
+        const uint32_t d = (h[v] != 0) != (c[v] != 0);
+        a += d;
+        b += d & (uint32_t)(colmap[v] >= 0);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       a += __shfl_xor(a, off);
@@ -513,7 +527,8 @@ extern "C" ldpc_status ldpc_count_errors(ldpc_encoder_t e, const uint8_t *hard, 
   if (batch == 0) return LDPC_OK;
   if (!hard || !cw) return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
   const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)batch + 3) / 4, 2048);
-  hipLaunchKernelGGL(count_errors_kernel, dim3(blocks), dim3(256), 0, stream, hard, cw, e->d_colmap, e->n, batch,
+  const bool vec = (e->n & 3) == 0 && ((uintptr_t)hard & 3) == 0 && ((uintptr_t)cw & 3) == 0;
+  hipLaunchKernelGGL(count_errors_kernel, dim3(blocks), dim3(256), 0, stream, hard, cw, e->d_colmap, e->n, batch, vec,
                      (unsigned long long *)counts);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;

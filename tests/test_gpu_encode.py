@@ -151,6 +151,21 @@ def test_count_errors(P, forms):
     enc.count_errors(torch.from_numpy(hard[:10]).cuda(), torch.from_numpy(cw[:10]).cuda(), counts)
     torch.cuda.synchronize()
     assert np.array_equal(counts.cpu().numpy(), want + OC.error_counts(hard[:10], cw[:10], form.info))
+    # rows not 4-byte aligned (one byte into a buffer), and a length not a multiple of 4
+    def shifted(a):
+        buf = torch.zeros(a.size + 1, dtype=torch.uint8, device="cuda")
+        buf[1:] = torch.from_numpy(a.ravel()).cuda()
+        return buf[1:].view(a.shape)
+    c2 = enc.count_errors(shifted(hard), shifted(cw))
+    code_i, form_i = _form(forms, "irregular")
+    enc_i = P.Encoder(P.Graph.from_code(code_i))
+    cw_i = rng.integers(0, 2, size=(77, code_i.n), dtype=np.uint8)
+    hard_i = cw_i ^ (rng.random(size=cw_i.shape) < 0.02).astype(np.uint8)
+    c3 = enc_i.count_errors(torch.from_numpy(hard_i).cuda(), torch.from_numpy(cw_i).cuda())
+    torch.cuda.synchronize()
+    assert code_i.n % 4 != 0
+    assert np.array_equal(c2.cpu().numpy(), want)
+    assert np.array_equal(c3.cpu().numpy(), OC.error_counts(hard_i, cw_i, form_i.info))
 
 
 def test_sweep_point_on_device_matches_oracle_pipeline(P, oracle_lib, forms):
