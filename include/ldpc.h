@@ -111,8 +111,13 @@ ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, i
 
 /* ---- stream form: one word per workgroup, state in LDS -------------------- */
 
-/* LDS bytes one word's decoding state needs (4 x edges rounded up to 16, + 80) and whether it fits
- * one workgroup of the current device (*supported = 1). */
+/* LDS bytes one word's decoding state needs and whether it fits one workgroup of the current
+ * device (*supported = 1).  The state is one FP32 message per edge plus 80 bytes, the message
+ * array rounded up to 16 bytes.  Codes outside the fixed degree pairs interleave the rows of 64
+ * checks at a time (the checks sorted by degree, ties by index); such a group spans 64 x its
+ * largest degree floats, the last group only up to its last entry, so the array exceeds the
+ * edge count only where a group mixes degrees.  *supported may be NULL (then no device is
+ * queried). */
 ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported);
 
 /*

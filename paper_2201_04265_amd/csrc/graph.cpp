@@ -45,7 +45,8 @@ void free_device(ldpc_graph_s *g) {
   if (g->d_var_ptr) (void)hipFree(g->d_var_ptr);
   if (g->d_var_edges) (void)hipFree(g->d_var_edges);
   if (g->d_var_xoff) (void)hipFree(g->d_var_xoff);
-  g->d_row_ptr = g->d_col_idx = g->d_var_ptr = g->d_var_edges = g->d_var_xoff = nullptr;
+  if (g->d_xslot) (void)hipFree(g->d_xslot);
+  g->d_row_ptr = g->d_col_idx = g->d_var_ptr = g->d_var_edges = g->d_var_xoff = g->d_xslot = nullptr;
 }
 
 std::vector<int32_t> byte_offsets(const std::vector<int32_t> &edges) {
@@ -159,6 +160,7 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, ldpc_format fmt, 
     delete g;
     return set_error(LDPC_ERR_UNSUPPORTED, "graph too large for 32-bit per-tile offsets");
   }
+  g->stream_x_floats = stream_x_floats(g);
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) {
     delete g;

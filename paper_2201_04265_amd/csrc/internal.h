@@ -21,6 +21,9 @@ struct ldpc_graph_s {
   int device = 0;
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_var_ptr = nullptr, *d_var_edges = nullptr;
   int32_t *d_var_xoff = nullptr;  // stream form: LDS byte offsets of the edges (var_edges order)
+  int64_t stream_x_floats = 0;     // stream form: floats of a word's message array in LDS
+  int32_t *d_xslot = nullptr;      // stream form, runtime degrees: start | degree << 16 per check slot
+  int32_t stream_slots = 0;        // entries of d_xslot (a multiple of 64)
   // Launch facts of the stream form, filled once on its first call (stream.hip).
   std::mutex stream_mu;
   bool stream_ready = false;
@@ -39,6 +42,9 @@ struct ldpc_encoder_s {
   uint64_t *d_A = nullptr;                // [rank4][kwp]: bit j of row r = message bit j enters parity r
   int32_t *d_colmap = nullptr;            // [n]: message index j, or -1 - r for the pivot of row r
 };
+
+// Floats of the stream form's per-word message array for this graph's layout (stream.hip).
+int64_t stream_x_floats(const ldpc_graph_s *g);
 
 // Device view passed to kernels by value.
 struct GraphDev {

@@ -178,8 +178,9 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
 // second halves of the prefix pairs, then the outputs.  Each row entry is read back
 // before it is overwritten by the same thread.  The arithmetic and its order are
 // those of check_core<DC, true>, so the outputs are the same bit for bit; the row
-// stands in for one of the three register arrays of -DC values.
-template <int DC>
+// stands in for one of the three register arrays of -DC values.  Entry j of the row
+// is row[j * STRIDE] (64 when the 64 checks of a wavefront interleave their rows).
+template <int DC, int STRIDE = 1>
 __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
   static_assert(DC < 0, "runtime degrees only");
   constexpr int DMAX = -DC;
@@ -188,7 +189,7 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (j < dc) {
-      const uint32_t b = __float_as_uint(row[j]);
+      const uint32_t b = __float_as_uint(row[j * STRIDE]);
       sx ^= b;
       const float q = __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown));
       qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
@@ -199,7 +200,7 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
   for (int j = 0; j < DMAX; ++j) {
     if (j < dc) {
       pd[j] = d;
-      row[j] = s;
+      row[j * STRIDE] = s;
       const float q = fabsf(qs[j]);
       if (j == 0) {
         d = q;
@@ -223,14 +224,14 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
       } else {
         // after one element the second half is exactly 1: written as the literal, as it
         // is a constant in check_core, so that the compiler forms the same operations
-        const float psj = j == 1 ? 1.0f : row[j];
+        const float psj = j == 1 ? 1.0f : row[j * STRIDE];
         od = fmaf(psj, d, pd[j] * s);
         os = fmaf(pd[j], d, psj * s);
       }
       const float ratio = os * __builtin_amdgcn_rcpf(od);
       const float mag = fabsf(__builtin_amdgcn_logf(ratio)) * kLn2;
       const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
-      row[j] = __uint_as_float(sgn | __float_as_uint(mag));
+      row[j * STRIDE] = __uint_as_float(sgn | __float_as_uint(mag));
       const float q = fabsf(qs[j]);
       const float dn = fmaf(s, q, d);
       s = fmaf(d, q, s);

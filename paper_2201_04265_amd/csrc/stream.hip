@@ -10,12 +10,15 @@
 // the next word from an atomic counter when theirs stops, so a word that needs
 // few iterations never waits for another.
 //
-// LDS per word (indexed in check-major edge order):
+// LDS per word:
 //   X [nnz] FP32  one message per edge, updated in place: the check phase reads the
 //                 v->c message (Eq. 6, clamped; stored with its variable's decision) and
 //                 leaves the c->v message (Eq. 5); the variable phase reads that and
 //                 leaves the next v->c message.  Each edge is touched by its own
-//                 check, then by its own variable.
+//                 check, then by its own variable.  Fixed check degrees keep each
+//                 check's messages as one row (rows placed for distinct LDS banks in
+//                 the variable phase); runtime degrees interleave the rows of the 64
+//                 checks one wavefront updates together (see stream_group_layout).
 // The channel LLRs are re-read from the caller's buffer in every variable phase and the
 // posterior of each variable phase (Eq. 7) goes straight to the caller's output row
 // (both coalesced, and the rewrites of a row stay in L2), so a word needs 4 bytes of
@@ -31,11 +34,8 @@ namespace ldpc {
 
 // X at LDS address 0 (so an edge's byte offset is its LDS address), then the word
 // index and the per-wave syndrome flags.
-__host__ __device__ inline size_t stream_x_bytes(int64_t nnz) { return ((size_t)nnz * 4 + 15) & ~size_t(15); }
-__host__ __device__ inline size_t stream_lds_bytes(int64_t nnz, int32_t n) {
-  (void)n;
-  return stream_x_bytes(nnz) + 80;
-}
+inline size_t stream_x_bytes(const ldpc_graph_s *g) { return ((size_t)g->stream_x_floats * 4 + 15) & ~size_t(15); }
+inline size_t stream_lds_bytes(const ldpc_graph_s *g) { return stream_x_bytes(g) + 80; }
 
 // Workgroup size limit per degree pair: every kernel fits the 128-VGPR budget of a
 // 1024-thread workgroup (the runtime-degree kernels keep half of their prefix pairs in
@@ -47,12 +47,13 @@ template <int DC, int DV, bool F64>
 __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     stream_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                          int max_iters, int early_stop, int *counter, uint8_t *__restrict__ hard,
-                         float *__restrict__ post, int32_t *__restrict__ iters) {
+                         float *__restrict__ post, int32_t *__restrict__ iters, const int32_t *__restrict__ xslot,
+                         int xslots, int xbytes) {
   constexpr int DCM = DC > 0 ? DC : -DC;
   constexpr int DVM = DV > 0 ? DV : -DV;
   extern __shared__ __align__(16) float smem[];
   float *X = smem;
-  int *s_misc = (int *)((char *)smem + stream_x_bytes(g.nnz));
+  int *s_misc = (int *)((char *)smem + xbytes);
   int &s_word = s_misc[0];
   int *s_unsat = s_misc + 4;  // [16] per wavefront: some check of the word is unsatisfied
   const int t = threadIdx.x, NT = blockDim.x;
@@ -80,23 +81,25 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
     int it = 0;
     for (;;) {
       uint32_t sxs = 0;  // OR of the checks' parities: bit 30 set iff one is unsatisfied
-      // two low-degree checks in flight per thread (more independent work per wave; the
-      // higher degrees would lose resident waves to the registers it takes)
-      constexpr int kCheckUnroll = DC > 0 && DC <= 8 ? 2 : 1;
+      if constexpr (DC > 0) {
+        // two low-degree checks in flight per thread (more independent work per wave;
+        // the higher degrees would lose resident waves to the registers it takes)
+        constexpr int kCheckUnroll = DC <= 8 ? 2 : 1;
 #pragma unroll kCheckUnroll
-      for (int c = t; c < g.m; c += NT) {
-        int e0, dc;
-        check_range<DC>(g, c, e0, dc);
-        uint32_t sx;
-        if constexpr (DC > 0) {  // whole rows move with 8- or 16-byte LDS accesses
+        for (int c = t; c < g.m; c += NT) {  // whole rows move with 8- or 16-byte LDS accesses
           float mv[DCM], ev[DCM];
-          lds_row_load<DC>(X + e0, dc, mv);
-          sx = check_core<DC, true>(mv, dc, ev);
-          lds_row_store<DC>(X + e0, dc, ev);
-        } else {  // in place on the row, which also holds half of the prefix pairs
-          sx = check_core_row<DC>(X + e0, dc);
+          lds_row_load<DC>(X + c * DC, DC, mv);
+          sxs |= check_core<DC, true>(mv, DC, ev);
+          lds_row_store<DC>(X + c * DC, DC, ev);
         }
-        sxs |= sx;
+      } else {
+        // one check per slot (a multiple of 64 slots; empty ones have degree 0), in place
+        // on its interleaved row, which also holds half of the prefix pairs
+        for (int sl = t; sl < xslots; sl += NT) {
+          const uint32_t info = (uint32_t)xslot[sl];
+          const int dc = (int)(info >> 16);
+          if (dc) sxs |= check_core_row<DC, 64>(X + (info & 0xffffu), dc);
+        }
       }
       const unsigned long long b = __ballot(syndrome_bit(sxs));
       if ((t & 63) == 0) s_unsat[wave] = b != 0ull;
@@ -180,7 +183,7 @@ using namespace ldpc;
 
 namespace {
 using StreamKernel = void (*)(GraphDev, const float *, const double *, int, int, int, int *, uint8_t *, float *,
-                              int32_t *);
+                              int32_t *, const int32_t *, int, int);
 
 // The kernel for a graph's degrees and the LLR precision (FP32 or FP64 input).
 StreamKernel pick_stream(const ldpc_graph_s *g, int &max_threads, bool f64 = false) {
@@ -226,6 +229,50 @@ int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
   return best_nt;
 }
 
+// Runtime check degrees: the checks, sorted by degree (ties in index order), are dealt
+// in groups of 64, one group per wavefront pass of the check phase.  Group i starts at
+// float start_i and holds entry j of its l-th check at start_i + 64 j + l, so the 64
+// lanes of a wavefront read and write 64 consecutive floats (64 distinct LDS banks).
+// A group spans 64 x its largest degree floats (the last one only up to its last
+// entry); when every group has one degree (quasi-cyclic codes with a circulant size
+// that is a multiple of 64, and every fixed degree) that is exactly the edge count.
+// Each check reads and writes only its own entries, so the placement does not change
+// any result.  For quasi-cyclic codes the stable sort keeps each block row's checks
+// consecutive and 64-aligned, so the 64 variables a wavefront updates (consecutive
+// columns of one circulant) also reach 64 distinct banks.
+struct StreamGroupLayout {
+  std::vector<int32_t> slot;  // [64 x groups]: start float | degree << 16 (0 = no check)
+  std::vector<int32_t> pos;   // [nnz]: float index of each edge (CSR order)
+  int64_t floats = 0;
+};
+
+StreamGroupLayout stream_group_layout(const ldpc_graph_s *g) {
+  StreamGroupLayout L;
+  const int m = g->m;
+  std::vector<int32_t> order(m);
+  for (int c = 0; c < m; ++c) order[c] = c;
+  auto deg = [&](int c) { return g->row_ptr[c + 1] - g->row_ptr[c]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return deg(a) < deg(b); });
+  const int groups = (m + 63) / 64;
+  L.slot.assign((size_t)groups * 64, 0);
+  L.pos.assign((size_t)g->nnz, 0);
+  int64_t start = 0;
+  for (int gi = 0; gi < groups; ++gi) {
+    const int cnt = std::min(64, m - 64 * gi);
+    int dmax = 0;
+    for (int l = 0; l < cnt; ++l) {
+      const int c = order[64 * gi + l], d = deg(c);
+      dmax = std::max(dmax, d);
+      const int64_t base = start + l;
+      L.slot[(size_t)64 * gi + l] = base < 65536 ? (int32_t)(base | ((int64_t)d << 16)) : 0;
+      for (int j = 0; j < d; ++j) L.pos[(size_t)g->row_ptr[c] + j] = (int32_t)std::min<int64_t>(base + 64 * j, INT32_MAX);
+    }
+    start += gi + 1 < groups ? 64 * (int64_t)dmax : 64 * (int64_t)(dmax - 1) + cnt;
+  }
+  L.floats = start;
+  return L;
+}
+
 // Where the check rows sit in LDS.  For a fixed check degree any order of the rows
 // gives the same results (each check reads and writes only its own row), so the rows
 // are placed in the order that keeps the LDS banks of the 64 variables a wavefront
@@ -236,8 +283,7 @@ int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
 std::vector<int32_t> stream_edge_offsets(const ldpc_graph_s *g) {
   const size_t E = (size_t)g->nnz;
   std::vector<int32_t> off(E);
-  const bool fixed = g->dc_min == g->dc_max && g->m >= 2;
-  if (!fixed) {
+  if (g->m < 2) {
     for (size_t p = 0; p < E; ++p) off[p] = g->var_edges[p] * 4;
     return off;
   }
@@ -314,7 +360,19 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
   LDPC_HIP_CHECK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   g->stream_lds_limit = lim;
   if (lds + 64 <= (size_t)lim) {
-    const std::vector<int32_t> off = stream_edge_offsets(g);
+    std::vector<int32_t> off;
+    if (kernel_kind(g) < KIND_G8) {
+      off = stream_edge_offsets(g);
+    } else {
+      const StreamGroupLayout L = stream_group_layout(g);
+      off.resize((size_t)g->nnz);
+      for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g->var_edges[p]] * 4;
+      if (!g->d_xslot) {
+        LDPC_HIP_CHECK(hipMalloc((void **)&g->d_xslot, L.slot.size() * sizeof(int32_t)));
+        g->stream_slots = (int32_t)L.slot.size();
+      }
+      LDPC_HIP_CHECK(hipMemcpy(g->d_xslot, L.slot.data(), L.slot.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     LDPC_HIP_CHECK(hipMemcpy(g->d_var_xoff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   if (lds + 64 > (size_t)lim) {  // cannot run; remember the limit only
@@ -346,9 +404,14 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
 }
 }  // namespace
 
+int64_t stream_x_floats(const ldpc_graph_s *g) {
+  if (kernel_kind(g) < KIND_G8) return g->nnz;  // fixed degrees: one row per check
+  return stream_group_layout(g).floats;
+}
+
 extern "C" ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported) {
   if (!g) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
-  const size_t b = stream_lds_bytes(g->nnz, g->n);
+  const size_t b = stream_lds_bytes(g);
   if (bytes) *bytes = b;
   if (supported) {
     int dev = 0, lim = 0;
@@ -365,7 +428,7 @@ ldpc_status stream_ready_for(ldpc_graph_s *g, int32_t threads) {
   if (threads > max_threads)
     return set_error(LDPC_ERR_INVALID_ARG,
                      "threads above " + std::to_string(max_threads) + " for this code's check degree");
-  const size_t lds = stream_lds_bytes(g->nnz, g->n);
+  const size_t lds = stream_lds_bytes(g);
   ldpc_status st = stream_prepare(g, k, max_threads, lds);
   if (st != LDPC_OK) return st;
   if (lds + 64 > (size_t)g->stream_lds_limit)
@@ -381,7 +444,7 @@ ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64,
   if (batch == 0) return LDPC_OK;
   int max_threads = 1024;
   StreamKernel k = pick_stream(g, max_threads, llr_f64);
-  const size_t lds = stream_lds_bytes(g->nnz, g->n);
+  const size_t lds = stream_lds_bytes(g);
   const int nt = threads ? threads : stream_threads(g, max_threads, batch);
   if (nt == 0) return set_error(LDPC_ERR_UNSUPPORTED, "stream kernel cannot be resident");
   int per_cu = 0;
@@ -398,7 +461,8 @@ ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64,
   LDPC_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, stream, graph_dev(g),
                      llr_f64 ? nullptr : (const float *)llr, llr_f64 ? (const double *)llr : nullptr, (int)batch,
-                     (int)max_iters, (int)(early_stop != 0), counter, hard_bits, posterior, iters_used);
+                     (int)max_iters, (int)(early_stop != 0), counter, hard_bits, posterior, iters_used,
+                     (const int32_t *)g->d_xslot, (int)g->stream_slots, (int)stream_x_bytes(g));
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;
 }

@@ -60,6 +60,13 @@ def stream_supported(graph: Graph) -> bool:
     return bool(ok.value)
 
 
+def stream_lds_bytes(graph: Graph) -> int:
+    """LDS bytes of one word's state in the stream form."""
+    nb = ctypes.c_size_t()
+    check("ldpc_stream_lds_bytes", lib().ldpc_stream_lds_bytes(graph.handle, ctypes.byref(nb), None))
+    return int(nb.value)
+
+
 def decode_stream(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = True, threads: int = 0,
                   workspace: torch.Tensor | None = None, out=None, stream=None):
     """Stream form (one word per workgroup, state in LDS); same outputs as decode()."""

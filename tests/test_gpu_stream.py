@@ -130,3 +130,57 @@ def test_generic_high_degree_codes_every_workgroup_size(P):
     for nt in (1024, 512):
         a, b = both(P, g, x.cpu().numpy(), 12, True, nt)
         same(a, b)
+
+
+FIXED_PAIRS = {(6, 3), (4, 3), (12, 3), (15, 3), (12, 6), (12, 9)}
+
+
+def _expected_lds_bytes(code):
+    """The documented size: fixed degree pairs keep one row per check (4 bytes per edge);
+    other codes interleave 64 degree-sorted checks per group, a group spanning 64 x its
+    largest degree floats (the last one up to its last entry)."""
+    rd = code.row_degrees()
+    cd = np.bincount(code.indices, minlength=code.n)
+    if rd.min() == rd.max() and cd.min() == cd.max() and (int(rd[0]), int(cd[0])) in FIXED_PAIRS:
+        floats = code.nnz
+    else:
+        d = np.sort(rd, kind="stable")
+        groups = [d[i:i + 64] for i in range(0, len(d), 64)]
+        floats = sum(64 * int(gr.max()) for gr in groups[:-1]) + 64 * (int(groups[-1].max()) - 1) + len(groups[-1])
+    return (floats * 4 + 15) // 16 * 16 + 80
+
+
+def _irregular_code(seed, m, n, dmin, dmax):
+    rng = np.random.default_rng(seed)
+    chk, var = [], []
+    for c in range(m):
+        vs = rng.choice(n, size=int(rng.integers(dmin, dmax + 1)), replace=False)
+        chk += [c] * len(vs)
+        var += list(vs)
+    return codes.from_edges(m, n, np.array(chk), np.array(var))
+
+
+def test_lds_bytes_of_the_interleaved_layout(P):
+    qc = W.code("c4_5")  # quasi-cyclic, circulant 128: every group has one degree
+    assert P.stream_lds_bytes(P.Graph.from_code(qc)) == (qc.nnz * 4 + 15) // 16 * 16 + 80
+    for name in ("c2", "c5", "paper_r12"):  # fixed degree pairs
+        c = W.code(name)
+        assert P.stream_lds_bytes(P.Graph.from_code(c)) == (c.nnz * 4 + 15) // 16 * 16 + 80
+    for seed, m, n in ((1, 50, 200), (2, 300, 700), (3, 1500, 4000)):
+        c = _irregular_code(seed, m, n, 2, 24)
+        got = P.stream_lds_bytes(P.Graph.from_code(c))
+        assert got == _expected_lds_bytes(c)
+        print(seed, m, n, "edges", c.nnz, "LDS bytes", got, flush=True)
+        assert got >= c.nnz * 4
+
+
+@pytest.mark.parametrize("threads", [0, 256, 1024])
+def test_many_check_groups_equal_plain(P, threads):
+    """An irregular code with 24 groups of 64 checks (more than one pass of the check phase
+    for every workgroup size), mixed degrees 3..20 inside groups at class boundaries."""
+    c = _irregular_code(5, 1500, 3000, 3, 20)
+    g = P.Graph.from_code(c)
+    assert P.stream_supported(g)
+    llr = np.random.default_rng(6).normal(1.8, 2.0, size=(150, c.n)).astype(np.float32)
+    a, b = both(P, g, llr, 20, True, threads)
+    same(a, b)
