@@ -241,6 +241,31 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
   return sx;
 }
 
+// check_core_row for a degree that is the same across the wavefront: a switch to the
+// instance compiled for that exact degree, whose degree tests all fold away (the
+// arithmetic is the same source, so the same bits as the runtime-degree form).
+template <int DC, int STRIDE>
+__device__ __forceinline__ uint32_t check_core_row_uniform(float *row, int dcu) {
+  static_assert(DC < 0, "runtime degrees only");
+  uint32_t sx = 0;
+  switch (dcu) {
+#define LDPC_ROW_CASE(D)                                               \
+  case D:                                                              \
+    if constexpr (D <= -DC) sx = check_core_row<-D, STRIDE>(row, D); \
+    break;
+    LDPC_ROW_CASE(2) LDPC_ROW_CASE(3) LDPC_ROW_CASE(4) LDPC_ROW_CASE(5) LDPC_ROW_CASE(6) LDPC_ROW_CASE(7)
+    LDPC_ROW_CASE(8) LDPC_ROW_CASE(9) LDPC_ROW_CASE(10) LDPC_ROW_CASE(11) LDPC_ROW_CASE(12) LDPC_ROW_CASE(13)
+    LDPC_ROW_CASE(14) LDPC_ROW_CASE(15) LDPC_ROW_CASE(16) LDPC_ROW_CASE(17) LDPC_ROW_CASE(18) LDPC_ROW_CASE(19)
+    LDPC_ROW_CASE(20) LDPC_ROW_CASE(21) LDPC_ROW_CASE(22) LDPC_ROW_CASE(23) LDPC_ROW_CASE(24) LDPC_ROW_CASE(25)
+    LDPC_ROW_CASE(26) LDPC_ROW_CASE(27) LDPC_ROW_CASE(28) LDPC_ROW_CASE(29) LDPC_ROW_CASE(30) LDPC_ROW_CASE(31)
+    LDPC_ROW_CASE(32)
+#undef LDPC_ROW_CASE
+    default:
+      break;
+  }
+  return sx;
+}
+
 // Syndrome bit of a check from the value check_core returned for stored messages.
 __device__ __forceinline__ int syndrome_bit(uint32_t sx) { return (int)((sx >> 30) & 1u); }
 

@@ -98,7 +98,15 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         for (int sl = t; sl < xslots; sl += NT) {
           const uint32_t info = (uint32_t)xslot[sl];
           const int dc = (int)(info >> 16);
-          if (dc) sxs |= check_core_row<DC, 64>(X + (info & 0xffffu), dc);
+          float *row = X + (info & 0xffffu);
+          // one degree across the wavefront (every group of a quasi-cyclic code): the
+          // code compiled for that degree, free of per-entry degree tests
+          const int dcu = __builtin_amdgcn_readfirstlane(dc);
+          if (__ballot(dc != dcu) == 0ull) {
+            sxs |= check_core_row_uniform<DC, 64>(row, dcu);
+          } else if (dc) {
+            sxs |= check_core_row<DC, 64>(row, dc);
+          }
         }
       }
       const unsigned long long b = __ballot(syndrome_bit(sxs));
@@ -134,23 +142,48 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       // X is the kernel's only LDS, so it starts at LDS address 0 (checked on the host)
       // and an edge's byte offset is its LDS address.
       auto xat = [](int off) { return (__attribute__((address_space(3))) float *)(size_t)off; };
-      auto update = [&](int v, const VarIn &f) {
+      auto update_dv = [&](int v, const VarIn &f, int dv) __attribute__((always_inline)) {
         float ev[DVM], pre[DVM];
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < f.dv) ev[j] = *xat(f.off[j]);
+          if (DV > 0 || j < dv) ev[j] = *xat(f.off[j]);
         float acc = f.r;
 #pragma unroll
         for (int j = 0; j < DVM; ++j) {
-          if (DV > 0 || j < f.dv) {
+          if (DV > 0 || j < dv) {
             pre[j] = acc;
             acc += ev[j];
           }
         }
         *(float *)((char *)prow + (uint32_t)v * 4u) = acc;
         const bool z = acc <= 0.0f;
-        var_exclusive<DV>(pre, ev, f.dv,
-                          [&](int j, float x) { *xat(f.off[j]) = v2c_store(x, z); });
+        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { *xat(f.off[j]) = v2c_store(x, z); });
+      };
+      auto update = [&](int v, const VarIn &f) {
+        if constexpr (DV > 0) {
+          update_dv(v, f, DV);
+        } else {  // one degree across the active lanes (a circulant's columns): the code
+                  // compiled for that degree
+          const int dvu = __builtin_amdgcn_readfirstlane(f.dv);
+          if (__ballot(f.dv != dvu) == 0ull) {
+            switch (dvu) {
+#define LDPC_VAR_CASE(D)                      \
+  case D:                                     \
+    if constexpr (D <= DVM) update_dv(v, f, D); \
+    break;
+              LDPC_VAR_CASE(1) LDPC_VAR_CASE(2) LDPC_VAR_CASE(3) LDPC_VAR_CASE(4) LDPC_VAR_CASE(5)
+              LDPC_VAR_CASE(6) LDPC_VAR_CASE(7) LDPC_VAR_CASE(8) LDPC_VAR_CASE(9) LDPC_VAR_CASE(10)
+              LDPC_VAR_CASE(11) LDPC_VAR_CASE(12) LDPC_VAR_CASE(13) LDPC_VAR_CASE(14) LDPC_VAR_CASE(15)
+              LDPC_VAR_CASE(16)
+#undef LDPC_VAR_CASE
+              default:
+                update_dv(v, f, dvu);  // degree 0: the posterior is the channel value
+                break;
+            }
+          } else {
+            update_dv(v, f, f.dv);
+          }
+        }
       };
       const int vlast = g.n - 1;
       VarIn fa, fb;
