@@ -42,11 +42,11 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "5dee99563a4c5f28711cf5a5e60cccaff6ce8079", "bytes_per_launch": 84875476180, "read_bytes": 14700759316,
-               "write_bytes": 70174716864},
+               "sha1": "476d270502e66176c1ba2d904adac78d0e9e9a7b", "bytes_per_launch": 84696553166, "read_bytes": 14743626542,
+               "write_bytes": 69952926624},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "ac543692212e8f39a6cc00e1706bd5dcba26a8dd", "bytes_per_launch": 1639487460116, "read_bytes": 959511257396,
-                "write_bytes": 679976202720},
+                "sha1": "e57370e3e7bb8656578aacad7c5266ca63170171", "bytes_per_launch": 1639412715159, "read_bytes": 959429640055,
+                "write_bytes": 679983075104},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
