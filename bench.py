@@ -42,8 +42,8 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "f308def61f87e501c131d9506e10f43222cd3313", "bytes_per_launch": 84639232084, "read_bytes": 14710364948,
-               "write_bytes": 69928867136},
+               "sha1": "1a50d7bdc2ab2d6059afaecaabae277e24521aa9", "bytes_per_launch": 84596803490, "read_bytes": 14625615490,
+               "write_bytes": 69971188000},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
                 "sha1": "e57370e3e7bb8656578aacad7c5266ca63170171", "bytes_per_launch": 1639412715159, "read_bytes": 959429640055,
                 "write_bytes": 679983075104},

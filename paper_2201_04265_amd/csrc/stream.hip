@@ -406,6 +406,8 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
       off = stream_edge_offsets(g);
     } else {
       const StreamGroupLayout L = stream_group_layout(g);
+      if (L.floats != g->stream_x_floats)  // the size the LDS was sized with
+        return set_error(LDPC_ERR_DEVICE, "stream layout size disagrees with the graph's LDS size");
       off.resize((size_t)g->nnz);
       for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g->var_edges[p]] * 4;
       if (!g->d_xslot) {
@@ -447,7 +449,16 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
 
 int64_t stream_x_floats(const ldpc_graph_s *g) {
   if (kernel_kind(g) < KIND_G8) return g->nnz;  // fixed degrees: one row per check
-  return stream_group_layout(g).floats;
+  // the group spans of stream_group_layout, from the sorted degrees alone
+  std::vector<int32_t> deg(g->m);
+  for (int c = 0; c < g->m; ++c) deg[c] = g->row_ptr[c + 1] - g->row_ptr[c];
+  std::sort(deg.begin(), deg.end());
+  int64_t floats = 0;
+  for (int i0 = 0; i0 < g->m; i0 += 64) {
+    const int cnt = std::min(64, g->m - i0), dmax = deg[i0 + cnt - 1];
+    floats += i0 + 64 < g->m ? 64 * (int64_t)dmax : 64 * (int64_t)(dmax - 1) + cnt;
+  }
+  return floats;
 }
 
 extern "C" ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported) {
