@@ -37,7 +37,7 @@ def gpu_grads(P, g, llr, w, cw):
     loss = bce(post, torch.from_numpy(cw.astype(np.float32)).cuda())
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), post.detach().cpu().numpy(), x.grad.cpu().numpy(), wt.grad.cpu().numpy()
+    return float(loss.detach()), post.detach().cpu().numpy(), x.grad.cpu().numpy(), wt.grad.cpu().numpy()
 
 
 @pytest.mark.parametrize("name,cfg,T", [("c5", 5, 10), ("c1", 1, 7), ("c3", 3, 4)])
