@@ -128,7 +128,18 @@ def make_inputs(args, torch):
     return code, ebn0s, llr, cw
 
 
-def cpu_baseline(code, ebn0s, sample):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(code, ebn0s, sample, sample_one=64):
     import oracle
     from synth import workloads as W
 
@@ -143,11 +154,24 @@ def cpu_baseline(code, ebn0s, sample):
         t_total += time.perf_counter() - t0
         words += sample
         iters += int(it.sum())
+    # the same oracle on one thread (the paper's single-process reference), smaller sample
+    w1 = i1 = 0
+    t1 = 0.0
+    for key, e in enumerate(ebn0s):
+        llr = W.words("c2", 2, key, e, 0, sample_one, fp32=True).llr
+        t0 = time.perf_counter()
+        _, _, it, _ = oracle.decode(code, llr, MAX_ITERS, True, 1)
+        t1 += time.perf_counter() - t0
+        w1 += sample_one
+        i1 += int(it.sum())
     return {"value": words * code.n / t_total / 1e9, "unit": "coded Gbit/s", "cores": threads, "kind": "oracle",
             "edge_updates_per_s": iters * code.nnz / t_total,
             "sample": f"first {sample} words of each of the {len(ebn0s)} Eb/N0 points ({words} words), "
                       f"FP64 C oracle, max {MAX_ITERS} iterations, early stop, {threads} threads; {t_total:.1f}s",
-            "cpu": platform.processor() or platform.machine()}
+            "affinity_cores": len(os.sched_getaffinity(0)), "cpu": cpu_model(),
+            "one_thread": {"value": w1 * code.n / t1 / 1e9, "unit": "coded Gbit/s",
+                           "edge_updates_per_s": i1 * code.nnz / t1,
+                           "sample": f"first {sample_one} words of each point ({w1} words), 1 thread; {t1:.1f}s"}}
 
 
 def time_launches(torch, fn, steps, warmup, stream):
@@ -162,6 +186,60 @@ def time_launches(torch, fn, steps, warmup, stream):
         b.record(stream)
     torch.cuda.synchronize()
     return [a.elapsed_time(b) for a, b in ev]
+
+
+def fixed_run(torch, fn, stream, words, code, form):
+    """One warm-up and one timed launch without early stop: every word runs all MAX_ITERS
+    iterations, so every iteration is useful and the roofline needs no iteration counts."""
+    ms = time_launches(torch, fn, 1, 1, stream)[0]
+    eu = words * MAX_ITERS * code.nnz / (ms * 1e-3)
+    d = {"ms": ms, "coded_gbit_s": words * code.n / (ms * 1e-3) / 1e9, "edge_updates_per_s": eu}
+    if form == "stream":
+        d["valu_frac"] = eu * STREAM_VALU_SLOTS_PER_EDGE / (VALU_PEAK_TOPS * 1e12)
+    else:
+        alg = words * (MAX_ITERS * bytes_per_word_iteration(code.n, code.nnz) + io_bytes_per_word(code.n))
+        d["hbm_alg_gb_s"] = alg / (ms * 1e-3) / 1e9
+        d["hbm_alg_frac"] = d["hbm_alg_gb_s"] / HBM_PEAK_GBS
+    return d
+
+
+def end_to_end(torch, P, g, code, llr_point, stream):
+    """One Eb/N0 point (llr_point, on the device) through pinned host memory: host-to-device
+    copy of the LLRs, stream-form decode, device-to-host copy of hard bits, posteriors and
+    iterations, on one stream; HIP events around each part."""
+    B = llr_point.shape[0]
+    h_llr = torch.empty(llr_point.shape, dtype=torch.float32, pin_memory=True)
+    h_llr.copy_(llr_point)
+    h_hard = torch.empty(llr_point.shape, dtype=torch.uint8, pin_memory=True)
+    h_post = torch.empty(llr_point.shape, dtype=torch.float32, pin_memory=True)
+    h_it = torch.empty((B,), dtype=torch.int32, pin_memory=True)
+    d_llr = torch.empty_like(llr_point)
+    outs = (torch.empty(llr_point.shape, dtype=torch.uint8, device="cuda"), torch.empty_like(llr_point),
+            torch.empty((B,), dtype=torch.int32, device="cuda"))
+    ws = torch.empty((256,), dtype=torch.uint8, device="cuda")
+
+    def once(ev):
+        ev[0].record(stream)
+        d_llr.copy_(h_llr, non_blocking=True)
+        ev[1].record(stream)
+        P.decode_stream(g, d_llr, MAX_ITERS, True, workspace=ws, out=outs)
+        ev[2].record(stream)
+        h_hard.copy_(outs[0], non_blocking=True)
+        h_post.copy_(outs[1], non_blocking=True)
+        h_it.copy_(outs[2], non_blocking=True)
+        ev[3].record(stream)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(3)]
+    for ev in evs:
+        once(ev)
+    torch.cuda.synchronize()
+    parts = [[ev[i].elapsed_time(ev[i + 1]) for i in range(3)] for ev in evs[1:]]
+    h2d, dec, d2h = (sum(p[i] for p in parts) / len(parts) for i in range(3))
+    total = h2d + dec + d2h
+    return {"words": B, "ms": total, "coded_gbit_s": B * code.n / (total * 1e-3) / 1e9, "h2d_ms": h2d,
+            "decode_ms": dec, "d2h_ms": d2h, "host_bytes": B * code.n * 9 + 4 * B,
+            "note": "pinned host buffers, one stream, copies not overlapped with the decode; the library's "
+                    "boundary takes device buffers, so this is context, not the headline value"}
 
 
 def summarize(torch, name, ms, outs, cw, ebn0s, B, code, extra):
@@ -262,6 +340,25 @@ def bench_c4(args, torch, P):
             P.decode(g, x, MAX_ITERS, True, workspace=ws, out=o)
 
     ms_plain = time_launches(torch, plain, args.steps, args.warmup, stream)
+    # the same per-code launches on six concurrent streams (default priority), forked from and
+    # joined back into the timing stream
+    side = [torch.cuda.Stream() for _ in graphs]
+
+    def plain_concurrent():
+        fork = torch.cuda.Event()
+        fork.record(stream)
+        joins = []
+        for s_, g_, x_, ws_, o_ in zip(side, graphs, llrs, wss, pouts):
+            s_.wait_event(fork)
+            with torch.cuda.stream(s_):
+                P.decode(g_, x_, MAX_ITERS, True, workspace=ws_, out=o_)
+            e = torch.cuda.Event()
+            e.record(s_)
+            joins.append(e)
+        for e in joins:
+            stream.wait_event(e)
+
+    ms_plain_conc = time_launches(torch, plain_concurrent, args.steps, args.warmup, stream)
     batch = P.Batch(graphs, llrs, MAX_ITERS)
     shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True)
     resolved, _ = batch.resolve(shape)
@@ -314,6 +411,7 @@ def bench_c4(args, torch, P):
             "config": {"workload": "4096 words round-robin over six seeded codes, each at its own Eb/N0 in [1,4] dB, "
                                    "max 50 iterations, early stop"},
             "batched_ms": avg(ms_batched), "batched_plan_ms": avg(ms_plan), "per_code_plain_ms": avg(ms_plain),
+            "per_code_plain_six_streams_ms": avg(ms_plain_conc),
             "speedup_vs_per_code_plain": avg(ms_plain) / avg(ms_batched),
             "batched_with_stream_codes_ms": avg(ms_hybrid),
             "stream_codes": [codes[i].name for i, f in enumerate(fits) if f],
@@ -460,7 +558,7 @@ def bench_paper(args, torch, P):
             "cpu_baseline": {"value": cpu_us, "unit": "us/vector", "cores": top, "kind": "oracle",
                              "sample": f"first {sample} vectors of each code, FP64 C oracle, 10 iterations, "
                                        f"vectors split over threads as in Eq. 9",
-                             "thread_sweep": sweep, "cpu": platform.processor() or platform.machine()}}
+                             "thread_sweep": sweep, "cpu": cpu_model()}}
 
 
 def main():
@@ -477,6 +575,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="batched form with the library's default shape")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fixed", action="store_true",
+                    help="skip the one fixed-iteration launch (no early stop) per form")
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="skip the end-to-end run of one Eb/N0 point through pinned host buffers")
     ap.add_argument("--no-generation", action="store_true",
                     help="skip timing the on-device encoder/channel and the on-device sweep")
     ap.add_argument("--paper-cpu-sample", type=int, default=64, help="vectors per code for the oracle thread sweep")
@@ -530,6 +632,12 @@ def main():
                                      {"kernel": "plain_decode_kernel<6,3>", "waves": 16})
         log(f"[bench] plain: {results['plain']['ms_per_step']:.1f} ms/step")
         plain_outs = outs
+        if not args.no_fixed:
+            fouts = tuple(torch.empty_like(t) for t in outs)
+            results["plain"]["fixed_iterations"] = fixed_run(
+                torch, lambda: P.decode(g, llr, MAX_ITERS, False, workspace=ws, out=fouts), stream, llr.shape[0],
+                code, "plain")
+            del fouts
         del ws
         torch.cuda.empty_cache()
 
@@ -550,6 +658,9 @@ def main():
         if "plain" in results:
             results["batched"]["bitwise_equal_to_plain"] = all(
                 bool(torch.equal(a, b)) for a, b in zip(batch.outs[0], plain_outs))
+        if not args.no_fixed:
+            results["batched"]["fixed_iterations"] = fixed_run(
+                torch, lambda: batch.run(False, shape, ws), stream, llr.shape[0], code, "batched")
 
     if "stream" in forms:
         outs = (torch.empty(llr.shape, dtype=torch.uint8, device="cuda"),
@@ -566,6 +677,17 @@ def main():
         if "plain" in results:
             r["bitwise_equal_to_plain"] = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain_outs))
         log(f"[bench] stream: {r['ms_per_step']:.1f} ms/step")
+        if not args.no_fixed:
+            fouts = tuple(torch.empty_like(t) for t in outs)
+            r["fixed_iterations"] = fixed_run(
+                torch, lambda: P.decode_stream(g, llr, MAX_ITERS, False, workspace=ws, out=fouts), stream,
+                llr.shape[0], code, "stream")
+            del fouts
+        if not args.no_e2e:
+            pt = len(ebn0s) // 2
+            r["end_to_end_one_point"] = dict(end_to_end(torch, P, g, code, llr[pt * B:(pt + 1) * B], stream),
+                                             ebn0_db=ebn0s[pt])
+            torch.cuda.empty_cache()
 
     generation = None
     if not args.no_generation:
