@@ -169,7 +169,8 @@ def cpu_baseline(code, ebn0s, sample, sample_one=64):
             "sample": f"first {sample} words of each of the {len(ebn0s)} Eb/N0 points ({words} words), "
                       f"FP64 C oracle, max {MAX_ITERS} iterations, early stop, {threads} threads; {t_total:.1f}s",
             "affinity_cores": len(os.sched_getaffinity(0)), "cpu": cpu_model(),
-            "one_thread": {"value": w1 * code.n / t1 / 1e9, "unit": "coded Gbit/s",
+            "us_per_vector": t_total / words * 1e6,
+            "one_thread": {"value": w1 * code.n / t1 / 1e9, "unit": "coded Gbit/s", "us_per_vector": t1 / w1 * 1e6,
                            "edge_updates_per_s": i1 * code.nnz / t1,
                            "sample": f"first {sample_one} words of each point ({w1} words), 1 thread; {t1:.1f}s"}}
 
@@ -694,6 +695,15 @@ def main():
         generation = bench_generation(args, torch, P, g, code, ebn0s, B, stream)
         log(f"[bench] on-device generation {generation['generate_ms']:.2f} ms, whole sweep {generation['sweep_ms']:.1f} ms")
 
+    for name, r in results.items():  # counter-measured HBM bytes beside the algorithmic ones
+        t = counter_traffic(name, B)
+        if t is not None:
+            r["counter_bytes_per_launch"] = t
+            r["counter_gb_s"] = t / (r["ms_per_step"] * 1e-3) / 1e9
+            r["counter_hbm_frac"] = r["counter_gb_s"] / HBM_PEAK_GBS
+            r["counter_note"] = ("HBM bytes of one launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a "
+                                 "1 GiB copy" + (" (taken with the library's default shape)" if name == "batched"
+                                                 else ""))
     head = results.get("stream") or results.get("batched") or results["plain"]
     result = {
         "metric": METRIC,
