@@ -425,6 +425,68 @@ def bench_c4(args, torch, P):
             "outputs_bitwise_equal": same, "per_code": per_code}
 
 
+def bench_c3(args, torch, P):
+    """Quasi-cyclic 22x44 protograph lifted by Z=256 (n=11264), 16384 words at 1.5 dB, at most 30
+    iterations with early stop.  Its word state (70400 edges) exceeds a workgroup's LDS, so the HBM
+    forms decode it: plain, batched persistent (autotuned shape) and split.  The words are drawn on
+    the device (ldpc_generate: Philox message bits, systematic encoding, AWGN; both parity-tested
+    against the oracle) because host generation of this batch takes minutes."""
+    from synth import workloads as W
+
+    cfg = W.C3
+    code = W.code(cfg["code"])
+    g = P.Graph.from_code(code)
+    B, T = cfg["batch"], cfg["max_iters"]
+    enc = P.Encoder(g)
+    s2 = 1.0 / (2.0 * (enc.k / enc.n) * 10 ** (cfg["ebn0"] / 10))
+    _, cw, llr = enc.generate(B, s2, GEN_SEED, 0, 0)
+    stream = torch.cuda.current_stream()
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
+    ws = torch.empty(P.workspace_size(g, B), dtype=torch.uint8, device="cuda")
+    outs = (torch.empty(llr.shape, dtype=torch.uint8, device="cuda"), torch.empty_like(llr),
+            torch.empty((B,), dtype=torch.int32, device="cuda"))
+    ms_plain = time_launches(torch, lambda: P.decode(g, llr, T, True, workspace=ws, out=outs), args.steps,
+                             args.warmup, stream)
+    del ws
+    batch = P.Batch([g], [llr], T)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True)
+    resolved, _ = batch.resolve(shape)
+    bws = batch.workspace(shape)
+    ms_batched = time_launches(torch, lambda: batch.run(True, shape, bws), args.steps, args.warmup, stream)
+    del bws
+    sws = torch.empty(P.split_workspace_size(g, B), dtype=torch.uint8, device="cuda")
+    souts = tuple(torch.empty_like(t) for t in outs)
+    ms_split = time_launches(torch, lambda: P.decode_split(g, llr, T, True, workspace=sws, out=souts), args.steps,
+                             args.warmup, stream)
+    it = outs[2].to(torch.int64)
+    useful = int(it.sum().item())
+    alg = useful * bytes_per_word_iteration(code.n, code.nnz) + B * io_bytes_per_word(code.n)
+    forms = {}
+    for name, ms, kern in (("plain", ms_plain, "plain_decode_kernel<-24,-16>"),
+                           ("batched", ms_batched, "multi_kernel_single<-24,-16>"),
+                           ("split", ms_split, "split_check_kernel<-24> / split_var_kernel<-16>")):
+        t = avg(ms) * 1e-3
+        forms[name] = {"ms_per_step": avg(ms), "coded_gbit_s": B * code.n / t / 1e9,
+                       "edge_updates_per_s": useful * code.nnz / t, "hbm_alg_gb_s": alg / t / 1e9,
+                       "hbm_alg_frac": alg / t / 1e9 / HBM_PEAK_GBS, "kernel": kern}
+    forms["batched"]["shape"] = resolved.as_dict(1)
+    same = all(bool(torch.equal(a, b)) for a, b in zip(batch.outs[0], outs)) and \
+        all(bool(torch.equal(a, b)) for a, b in zip(souts, outs))
+    errs = outs[0] != cw
+    best = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    return {"metric": "coded Gbit/s, quasi-cyclic n=11264 code, 16384 words at 1.5 dB; plain vs batched vs split",
+            "value": forms[best]["coded_gbit_s"], "unit": "coded Gbit/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": forms[best]["ms_per_step"], "higher_is_better": True,
+            "value_form": best, "dtype": "f32", "data": "synthetic (drawn on the device)",
+            "config": {"workload": "quasi-cyclic 22x44 protograph, Z=256, n=11264, %d edges; %d words at %.1f dB; "
+                                   "max %d iterations, early stop" % (code.nnz, B, cfg["ebn0"], T),
+                       "rate": enc.k / enc.n},
+            "forms": forms, "outputs_bitwise_equal": same, "mean_iters": float(it.float().mean().item()),
+            "words_at_max_iters": int((it == T).sum().item()), "ber_coded": float(errs.float().mean().item()),
+            "fer": float(errs.any(dim=1).float().mean().item()),
+            "stream_form": "unsupported: word state %d bytes exceeds LDS" % P.stream_lds_bytes(g)}
+
+
 def bench_c5(args, torch, P):
     """Unrolled (3,6) n=1024 decoder, 10 weighted iterations, 4096 words at 2.0 dB: forward, and
     forward + BCE loss + backward (gradients w.r.t. weights and channel LLRs)."""
@@ -565,8 +627,9 @@ def bench_paper(args, torch, P):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "paper"],
-                    help="c2: (3,6) n=4096 Eb/N0 sweep (default); c4: six-code mixed batch, batched vs per-code "
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "paper"],
+                    help="c2: (3,6) n=4096 Eb/N0 sweep (default); c3: quasi-cyclic n=11264 code, HBM forms; "
+                         "c4: six-code mixed batch, batched vs per-code "
                          "plain launches; c5: unrolled differentiable form, forward and forward+backward; "
                          "paper: Table I codes, per-vector time")
     ap.add_argument("--steps", type=int, default=5)
@@ -605,6 +668,9 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
         return
 
+    if args.workload == "c3":
+        print(json.dumps(bench_c3(args, torch, P)), flush=True)
+        return
     if args.workload == "c4":
         print(json.dumps(bench_c4(args, torch, P)), flush=True)
         return
