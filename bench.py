@@ -18,8 +18,17 @@ Also reported: edge updates/s (useful iterations only), per-point iterations /
 BER / FER, the roofline of the headline kernel -- the stream kernel is bound by
 VALU issue, so its figure is VALU issue slots per useful edge-iteration (counted
 in the compiled code) over the launch time against 256 CU x 64 lanes x 2.4 GHz;
-the HBM forms carry their byte rooflines -- and the FP64 CPU oracle timed on a
-bounded sample of the same words.
+the HBM forms carry their byte rooflines, beside the counter-measured bytes where
+rocprofv3 FETCH_SIZE / WRITE_SIZE runs exist for the kernel sources -- one extra
+launch per form with early stop off (every iteration useful), the stream form's
+end-to-end time for one point through pinned host memory, the on-device generation
+of the sweep (encoder + channel + error counts), and the FP64 CPU oracle timed on a
+bounded sample of the same words (all host threads, and one thread).
+
+Other workloads (--workload): c3, a quasi-cyclic n=11264 code whose word state
+exceeds LDS (HBM forms); c4, a six-code mixed batch (batched forms against per-code
+plain launches); c5, the unrolled differentiable form (forward, forward + adjoint);
+paper, the Table I codes (per-vector time, oracle thread sweep).
 """
 from __future__ import annotations
 
