@@ -51,8 +51,8 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTER_TRAFFIC = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "1a50d7bdc2ab2d6059afaecaabae277e24521aa9", "bytes_per_launch": 84596803490, "read_bytes": 14625615490,
-               "write_bytes": 69971188000},
+               "sha1": "a486dca8e51cf41c62c2126486d017e66fdecd77", "bytes_per_launch": 86295877364, "read_bytes": 14619706804,
+               "write_bytes": 71676170560},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
                 "sha1": "e57370e3e7bb8656578aacad7c5266ca63170171", "bytes_per_launch": 1639412715159, "read_bytes": 959429640055,
                 "write_bytes": 679983075104},
@@ -60,10 +60,11 @@ COUNTER_TRAFFIC = {
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
 # VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 178 VALU instructions per pair of degree-6 checks and 44 per pair of degree-3 variables
-# (both loops take two at a time), loop control included; one wave64 instruction = 64
-# lane-slots.  The exp2 / log2 / rcp among them add no issue cycles of their own.
-STREAM_VALU_SLOTS_PER_EDGE = 89 / 6.0 + 22 / 3.0
+# code: 178 VALU instructions per pair of degree-6 checks and 67 per three degree-3 variables
+# (the check loop takes two at a time, the variable loop three), loop control included; one
+# wave64 instruction = 64 lane-slots.  The exp2 / log2 / rcp among them add no issue cycles of
+# their own.
+STREAM_VALU_SLOTS_PER_EDGE = 89 / 6.0 + 67 / 9.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 

@@ -116,9 +116,10 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       for (int w = 0; w < W; ++w) any_unsat |= s_unsat[w];
       if ((early_stop && !any_unsat) || it == max_iters) break;  // same value in every thread
       // The global reads of a variable (its edge list as LDS byte offsets, its channel
-      // LLR) are issued one variable ahead, so their latency overlaps the work of the
-      // current one.  Two register sets alternate (variables are taken in pairs), so no
-      // loaded value has to be copied out of the way of the next load.
+      // LLR) are issued ahead of its update (two variables ahead for the low fixed
+      // degrees, one otherwise), so their latency overlaps the work on the ones before.
+      // Register sets rotate (variables are taken in threes or pairs), so no loaded
+      // value has to be copied out of the way of the next load.
       const float *__restrict__ lrow32 = llr32 + base;
       const double *__restrict__ lrow64 = llr64 + base;
       float *__restrict__ prow = post + base;
@@ -186,16 +187,36 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         }
       };
       const int vlast = g.n - 1;
-      VarIn fa, fb;
-      if (t < g.n) fetch(t, fa);
-      int v = t;
-      for (; v + NT < g.n; v += 2 * NT) {
-        fetch(v + NT, fb);
-        update(v, fa);
-        fetch(min(v + 2 * NT, vlast), fa);
-        update(v + NT, fb);
+      // low fixed degrees: three register sets, the reads two variables ahead (the
+      // higher degrees' sets would cost them resident waves)
+      if constexpr (DV > 0 && DV <= 3 && DC > 0 && DC <= 6) {
+        VarIn fa, fb, fc;
+        if (t < g.n) fetch(t, fa);
+        if (t + NT < g.n) fetch(t + NT, fb);
+        int v = t;
+        for (; v + 2 * NT < g.n; v += 3 * NT) {
+          fetch(v + 2 * NT, fc);
+          update(v, fa);
+          fetch(min(v + 3 * NT, vlast), fa);
+          update(v + NT, fb);
+          fetch(min(v + 4 * NT, vlast), fb);
+          update(v + 2 * NT, fc);
+        }
+        if (v < g.n) update(v, fa);
+        if (v + NT < g.n) update(v + NT, fb);
+      } else {
+        // two sets (for runtime degrees a third one of up to 16 offsets would spill)
+        VarIn fa, fb;
+        if (t < g.n) fetch(t, fa);
+        int v = t;
+        for (; v + NT < g.n; v += 2 * NT) {
+          fetch(v + NT, fb);
+          update(v, fa);
+          fetch(min(v + 2 * NT, vlast), fa);
+          update(v + NT, fb);
+        }
+        if (v < g.n) update(v, fa);
       }
-      if (v < g.n) update(v, fa);
       lds_barrier();  // also orders this iteration's reads of s_unsat before the next writes
       ++it;
     }

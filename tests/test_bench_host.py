@@ -30,7 +30,7 @@ def test_byte_model_of_the_hbm_forms():
 
 
 def test_valu_model_and_peaks():
-    assert bench.STREAM_VALU_SLOTS_PER_EDGE == pytest.approx(89 / 6 + 22 / 3)
+    assert bench.STREAM_VALU_SLOTS_PER_EDGE == pytest.approx(89 / 6 + 67 / 9)
     assert bench.VALU_PEAK_TOPS == pytest.approx(256 * 64 * 2.4e9 / 1e12)
     assert bench.HBM_PEAK_GBS == 8000.0
 
