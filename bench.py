@@ -90,7 +90,7 @@ def roofline(head, code, B):
                 "unit_of_work": "useful edge-iteration x VALU instructions per edge-iteration (%.2f lane-slots, "
                                 "compiled code)" % STREAM_VALU_SLOTS_PER_EDGE,
                 "traffic_note": "HBM bytes per launch (counters): messages stay in LDS; beyond the 9n bytes of "
-                                "I/O per word, posterior rewrites of each iteration that overflow L2 (19 % "
+                                "I/O per word, posterior rewrites of each iteration that overflow L2 (21 % "
                                 "of the HBM peak; the kernel is bound by VALU issue and LDS / barrier "
                                 "latency, and keeping them in LDS costs one resident word per CU)",
                 "hbm_alg_gb_s_equivalent": head["achieved_gb_s"]}
