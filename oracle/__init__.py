@@ -6,6 +6,9 @@ import it; the decoder package never does, and the two share no code.
 
 * ``decode``      -- flooding sum-product (Eqs. 4-8, Algorithm 1's flooding
                      order) with syndrome early stop, C (spa.c), FP64;
+* ``decode_ex``   -- the same from a given c->v state, returning the final state
+                     (one-step checks); ``store32=True`` selects the build of the same
+                     source that rounds every stored value to FP32 (spa.c header);
 * ``unrolled``    -- the per-edge-weighted unrolled form (C, FP64);
 * ``syndrome_ok`` -- H z^T = 0 test (Eq. 1);
 * ``bitwise_map`` -- exact bitwise MAP by enumerating every codeword (map.py);
@@ -26,34 +29,51 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_spa.so")
+_SO32 = os.path.join(_HERE, "_spa_store32.so")  # same source, stored values rounded to FP32
 _lib = None
+_lib32 = None
 
 
 def build() -> str:
-    """Compile spa.c with gcc into oracle/_spa.so (plain -O2, no fast-math, no FMA)."""
+    """Compile spa.c with gcc into oracle/_spa.so (plain -O2, no fast-math, no FMA), and the
+    FP32-storage build of the same source into oracle/_spa_store32.so."""
     src = os.path.join(_HERE, "spa.c")
-    tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src, "-lm", "-lpthread"])
-    os.replace(tmp, _SO)
+    for so, extra in ((_SO, []), (_SO32, ["-DORACLE_STORE32"])):
+        tmp = so + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared"] + extra +
+                              ["-o", tmp, src, "-lm", "-lpthread"])
+        os.replace(tmp, so)
     return _SO
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_SO):
-        build()
-    lib = ctypes.CDLL(_SO)
+def _open(path):
+    lib = ctypes.CDLL(path)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.oracle_decode.argtypes = [i32, i32, p, p, p, i64, i32, i32, i32, p, p, p, p]
     lib.oracle_decode.restype = ctypes.c_int
+    lib.oracle_decode_ex.argtypes = [i32, i32, p, p, p, i64, i32, i32, i32, p, p, p, p, p, p]
+    lib.oracle_decode_ex.restype = ctypes.c_int
     lib.oracle_unrolled.argtypes = [i32, i32, p, p, p, i64, i32, p, i32, p]
     lib.oracle_unrolled.restype = ctypes.c_int
     lib.oracle_syndrome_ok.argtypes = [i32, i32, p, p, p, i64, p]
     lib.oracle_syndrome_ok.restype = ctypes.c_int
-    _lib = lib
     return lib
+
+
+def _load(store32: bool = False):
+    global _lib, _lib32
+    if store32:
+        if _lib32 is None:
+            if not os.path.exists(_SO32):
+                build()
+            _lib32 = _open(_SO32)
+        return _lib32
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    _lib = _open(_SO)
+    return _lib
 
 
 def _ptr(a: np.ndarray):
@@ -91,6 +111,39 @@ def decode(code, llr, max_iters: int, early_stop: bool = True, nthreads: int | N
     if rc:
         raise RuntimeError(f"oracle_decode failed ({rc})")
     return hard, post, iters, conv
+
+
+def decode_ex(code, llr, max_iters: int, early_stop: bool = True, init_cv=None, store32: bool = False,
+              nthreads: int | None = None):
+    """Flooding sum-product from the c->v state init_cv [B, nnz] (CSR edge order; None = zeros).
+
+    Returns (hard, post, iters, converged, final_cv [B, nnz] f64): final_cv holds the c->v
+    messages of each word's last iteration (init_cv, or zeros, when it stops at 0).
+    store32 selects the FP32-storage build of the same source.
+    """
+    lib = _load(store32)
+    llr = np.ascontiguousarray(np.asarray(llr, dtype=np.float64))
+    if llr.ndim == 1:
+        llr = llr[None, :]
+    B, n = llr.shape
+    assert n == code.n
+    rp, ci = _csr(code)
+    nnz = int(rp[-1])
+    if init_cv is not None:
+        init_cv = np.ascontiguousarray(np.asarray(init_cv, dtype=np.float64))
+        assert init_cv.shape == (B, nnz)
+    hard = np.zeros((B, n), dtype=np.uint8)
+    post = np.zeros((B, n), dtype=np.float64)
+    iters = np.zeros(B, dtype=np.int32)
+    conv = np.zeros(B, dtype=np.uint8)
+    fin = np.zeros((B, nnz), dtype=np.float64)
+    rc = lib.oracle_decode_ex(code.m, code.n, _ptr(rp), _ptr(ci), _ptr(llr), B, int(max_iters),
+                              int(bool(early_stop)), int(nthreads or default_threads()),
+                              _ptr(init_cv) if init_cv is not None else None, _ptr(fin), _ptr(hard), _ptr(post),
+                              _ptr(iters), _ptr(conv))
+    if rc:
+        raise RuntimeError(f"oracle_decode_ex failed ({rc})")
+    return hard, post, iters, conv, fin
 
 
 def unrolled(code, llr, w):

@@ -25,6 +25,21 @@
  *       M^(t+1)_vc = clamp(R_v + sum_{c' != c} w^(t)_c'v E^(t)_c'v)
  *       L_v        = R_v + sum_c w^(T)_cv E^(T)_cv
  * with M^(1) = clamp(R).  All weights 1 gives the plain decoder without early stop.
+ *
+ * State in and out (for one-step checks and resumption): a decode may start from given
+ * c->v messages E^(0) instead of zeros.  Then the iteration-0 posterior is Eq. 7 on that
+ * state, L^(0) = R + sum_c E^(0)_cv, its decisions are tested first, and iteration 1
+ * forms M^(1) from E^(0) by Eq. 6; with E^(0) = 0 this is the decode above.  The state
+ * after the last iteration (E of iteration `iters`) can be returned.
+ *
+ * FP32-storage build (compiled with -DORACLE_STORE32): the same source, with every
+ * value the decoder keeps between steps -- R, each c->v and v->c message, each
+ * posterior -- rounded to FP32 where it is stored, while every formula is still
+ * evaluated in FP64.  It is the decoder an FP32 implementation would be if each of
+ * its stored values were correctly rounded, the reference point for how far FP32
+ * storage alone moves posteriors along a decoding trajectory.  (A build with FP32
+ * arithmetic throughout is not a usable reference: tanh(x / 2) rounds to 1 in FP32
+ * for x above about 18, so the tanh rule meets atanh(1) = inf at the clamp.)
  */
 #include <math.h>
 #include <pthread.h>
@@ -33,6 +48,12 @@
 #include <string.h>
 
 #define L_MAX 20.0
+
+#ifdef ORACLE_STORE32
+#define STORE(x) ((double)(float)(x))
+#else
+#define STORE(x) (x)
+#endif
 
 typedef struct {
   int32_t m, n;
@@ -94,7 +115,7 @@ static void variable_messages(const graph_t *g, const double *R, const double *E
         if (f == e) continue;
         s += w ? w[f] * E[f] : E[f];
       }
-      M[e] = clamp_llr(s);
+      M[e] = STORE(clamp_llr(s));
     }
   }
 }
@@ -108,7 +129,7 @@ static void check_messages(const graph_t *g, const double *M, double *E) {
         if (f == e) continue;
         p *= tanh(M[f] / 2.0);
       }
-      E[e] = 2.0 * atanh(p);
+      E[e] = STORE(2.0 * atanh(p));
     }
   }
 }
@@ -121,12 +142,12 @@ static void posterior(const graph_t *g, const double *R, const double *E, const 
       int64_t e = g->var_edges[i];
       s += w ? w[e] * E[e] : E[e];
     }
-    L[v] = s;
+    L[v] = STORE(s);
   }
 }
 
 typedef struct {
-  double *E, *M;
+  double *E, *M, *R;
   uint8_t *z;
 } scratch_t;
 
@@ -134,21 +155,31 @@ static int scratch_alloc(scratch_t *s, const graph_t *g) {
   size_t ne = (size_t)(g->nnz > 0 ? g->nnz : 1);
   s->E = (double *)malloc(ne * sizeof(double));
   s->M = (double *)malloc(ne * sizeof(double));
+  s->R = (double *)malloc(((size_t)g->n + 1) * sizeof(double));
   s->z = (uint8_t *)malloc((size_t)g->n + 1);
-  return (s->E && s->M && s->z) ? 0 : -1;
+  return (s->E && s->M && s->R && s->z) ? 0 : -1;
 }
 
 static void scratch_free(scratch_t *s) {
   free(s->E);
   free(s->M);
+  free(s->R);
   free(s->z);
 }
 
-/* One codeword of the plain decoder.  L receives the posterior. */
-static void decode_word(const graph_t *g, const double *R, int32_t T, int32_t early_stop, scratch_t *s,
-                        double *L, uint8_t *hard, int32_t *iters, uint8_t *conv) {
-  for (int64_t e = 0; e < g->nnz; e++) s->E[e] = 0.0;
-  for (int32_t v = 0; v < g->n; v++) L[v] = R[v];
+/* One codeword of the plain decoder.  L receives the posterior.  E0 (nullable) is the
+ * starting c->v state [nnz]; Eout (nullable) receives the state of the last iteration. */
+static void decode_word(const graph_t *g, const double *Rin, int32_t T, int32_t early_stop, scratch_t *s,
+                        const double *E0, double *Eout, double *L, uint8_t *hard, int32_t *iters, uint8_t *conv) {
+  double *R = s->R;
+  for (int32_t v = 0; v < g->n; v++) R[v] = STORE(Rin[v]);
+  if (E0) {
+    for (int64_t e = 0; e < g->nnz; e++) s->E[e] = STORE(E0[e]);
+    posterior(g, R, s->E, NULL, L);
+  } else {
+    for (int64_t e = 0; e < g->nnz; e++) s->E[e] = 0.0;
+    for (int32_t v = 0; v < g->n; v++) L[v] = R[v];
+  }
   hard_decide(g, L, s->z);
   int32_t t = 0;
   int ok = syndrome_zero(g, s->z);
@@ -164,6 +195,7 @@ static void decode_word(const graph_t *g, const double *R, int32_t T, int32_t ea
     if (t > T) t = T;
   }
   memcpy(hard, s->z, (size_t)g->n);
+  if (Eout) memcpy(Eout, s->E, (size_t)g->nnz * sizeof(double));
   *iters = t;
   *conv = (uint8_t)ok;
 }
@@ -195,6 +227,8 @@ typedef struct {
   int64_t b0, b1;
   int32_t T, early_stop;
   const double *w; /* unrolled form when non-NULL or when mode == 1 */
+  const double *E0; /* starting c->v state [B][nnz] (plain form, nullable) */
+  double *Eout;     /* final c->v state [B][nnz] (plain form, nullable) */
   int mode;        /* 0 plain, 1 unrolled */
   uint8_t *hard;
   double *post;
@@ -214,9 +248,10 @@ static void *worker(void *arg) {
   const int32_t n = j->g->n;
   for (int64_t b = j->b0; b < j->b1; b++) {
     const double *R = j->llr + (size_t)b * n;
+    const size_t eo = (size_t)b * (size_t)j->g->nnz;
     if (j->mode == 0)
-      decode_word(j->g, R, j->T, j->early_stop, &s, j->post + (size_t)b * n, j->hard + (size_t)b * n,
-                  j->iters + b, j->conv + b);
+      decode_word(j->g, R, j->T, j->early_stop, &s, j->E0 ? j->E0 + eo : NULL, j->Eout ? j->Eout + eo : NULL,
+                  j->post + (size_t)b * n, j->hard + (size_t)b * n, j->iters + b, j->conv + b);
     else
       unrolled_word(j->g, R, j->T, j->w, &s, j->post + (size_t)b * n);
   }
@@ -260,10 +295,12 @@ static int run_jobs(job_t *proto, int64_t B, int32_t nthreads) {
   return rc;
 }
 
-/* Plain decoder: llr [B][n] FP64 -> hard [B][n] (0/1), post [B][n], iters [B], conv [B]. */
-int oracle_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *llr,
-                  int64_t B, int32_t max_iters, int32_t early_stop, int32_t nthreads, uint8_t *hard, double *post,
-                  int32_t *iters, uint8_t *conv) {
+/* Plain decoder: llr [B][n] FP64 -> hard [B][n] (0/1), post [B][n], iters [B], conv [B].
+ * init_cv [B][nnz] (nullable): starting c->v messages, CSR edge order; final_cv [B][nnz]
+ * (nullable) receives the c->v messages of each word's last iteration. */
+int oracle_decode_ex(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *llr,
+                     int64_t B, int32_t max_iters, int32_t early_stop, int32_t nthreads, const double *init_cv,
+                     double *final_cv, uint8_t *hard, double *post, int32_t *iters, uint8_t *conv) {
   graph_t g;
   if (m <= 0 || n <= 0 || max_iters < 0 || B < 0) return -3;
   if (graph_init(&g, m, n, row_ptr, col_idx)) {
@@ -277,6 +314,8 @@ int oracle_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *c
   proto.T = max_iters;
   proto.early_stop = early_stop;
   proto.mode = 0;
+  proto.E0 = init_cv;
+  proto.Eout = final_cv;
   proto.hard = hard;
   proto.post = post;
   proto.iters = iters;
@@ -284,6 +323,13 @@ int oracle_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *c
   int rc = B > 0 ? run_jobs(&proto, B, nthreads) : 0;
   graph_free(&g);
   return rc;
+}
+
+int oracle_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *llr,
+                  int64_t B, int32_t max_iters, int32_t early_stop, int32_t nthreads, uint8_t *hard, double *post,
+                  int32_t *iters, uint8_t *conv) {
+  return oracle_decode_ex(m, n, row_ptr, col_idx, llr, B, max_iters, early_stop, nthreads, NULL, NULL, hard, post,
+                          iters, conv);
 }
 
 /* Unrolled weighted form: w [T][nnz] FP64 -> post [B][n]. */
