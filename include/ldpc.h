@@ -103,6 +103,24 @@ ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t 
                         uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used, void *workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/*
+ * ldpc_decode with the c->v state in and out (one-step checks of Eqs. 5-7 from a given
+ * state; resuming a decode).  init_cv: NULL, or device [batch][edges] FP32 c->v messages
+ * E^(0) in CSR edge order to start from instead of zeros.  Then the iteration-0 posterior
+ * is L^(0) = R + sum_c E^(0)_cv (Eq. 7 on that state, ascending check order), its
+ * decisions are tested first when early_stop is set (a word that stops there returns
+ * L^(0) and its decisions), and iteration 1 forms M^(1) = clamp(R + sum_{c'!=c} E^(0)_c'v)
+ * (Eq. 6).  final_cv: NULL, or device [batch][edges]: receives each word's c->v messages
+ * of its last iteration, E^(iters_used) (init_cv, or zeros without it, for a word that
+ * stops at 0).  With both NULL this is ldpc_decode; otherwise the same arguments, the
+ * same workspace and the same errors, plus LDPC_ERR_INVALID_ARG for a state pointer on
+ * a graph without edges.  The buffers are read or written only during the enqueued work.
+ */
+ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
+                           uint32_t flags, const float *init_cv, float *final_cv, uint8_t *hard_bits,
+                           float *posterior, int32_t *iters_used, void *workspace, size_t ws_bytes,
+                           hipStream_t stream);
+
 /* Decode with an explicit launch shape: waves per workgroup (1..16; ldpc_decode uses 16).
  * Same contract as ldpc_decode. */
 ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,

@@ -21,6 +21,10 @@
 //                   for running lanes
 // The egress recomputes each word's final posterior from its own E buffer with the
 // same summation as the variable phase, so it equals the L whose decisions stopped it.
+//
+// State in and out: a decode may start from caller c->v messages E^(0) (placed in E0,
+// then one variable phase on them gives L^(0), z^(0) and M^(1)), and may write each
+// word's E of its last iteration back out.
 #include "internal.h"
 #include "tile.h"
 
@@ -30,7 +34,8 @@ template <int DC, int DV>
 __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__restrict__ llr32,
                                                   const double *__restrict__ llr64, int B, int max_iters,
                                                   int early_stop, char *ws, uint8_t *__restrict__ hard,
-                                                  float *__restrict__ post, int32_t *__restrict__ iters) {
+                                                  float *__restrict__ post, int32_t *__restrict__ iters,
+                                                  const float *__restrict__ init_cv, float *__restrict__ final_cv) {
   __shared__ float stage[TW][TW + 1];
   __shared__ unsigned long long unsat_w[16];
   const int lane = lane_id();
@@ -42,6 +47,15 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
   const TileState st = tile_state_block(ws + (size_t)tile * tile_bytes(g.nnz, g.n), g.nnz, g.n);
 
   ingest_tile<DV>(g, llr32, llr64, cw0, nvalid, st, stage, wave, W, lane);
+  if (init_cv) {
+    ingest_edges(g, init_cv, cw0, nvalid, st.E0, stage, wave, W, lane);
+    for (int v = wave; v < g.n; v += W) {
+      int p0, dv;
+      var_range<DV>(g, v, p0, dv);
+      var_update<DV>(st.R, st.E0, st.M, g.var_edges, p0, dv, v, lane, true);
+    }
+    __syncthreads();
+  }
 
   bool active = lane < nvalid;
   int my_iters = 0;
@@ -72,7 +86,8 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
     __syncthreads();
   }
 
-  egress_tile<DV>(g, st, my_iters, cw0, nvalid, post, hard, stage, wave, W, lane);
+  egress_tile<DV>(g, st, my_iters, cw0, nvalid, post, hard, stage, wave, W, lane, 0, 1, init_cv != nullptr);
+  if (final_cv) egress_edges(g, st, my_iters, init_cv != nullptr, cw0, nvalid, final_cv, stage, wave, W, lane);
   if (wave == 0 && lane < nvalid) iters[cw0 + lane] = my_iters;
 }
 
@@ -88,16 +103,17 @@ template <int DC, int DV>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
     plain_decode_kernel_w8(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                            int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard,
-                           float *__restrict__ post, int32_t *__restrict__ iters) {
-  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters);
+                           float *__restrict__ post, int32_t *__restrict__ iters, const float *__restrict__ init_cv,
+                           float *__restrict__ final_cv) {
+  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters, init_cv, final_cv);
 }
 
 template <int DC, int DV>
 __global__ void __launch_bounds__(1024)
     plain_decode_kernel(GraphDev g, const float *__restrict__ llr32, const double *__restrict__ llr64, int B,
                         int max_iters, int early_stop, char *ws, uint8_t *__restrict__ hard, float *__restrict__ post,
-                        int32_t *__restrict__ iters) {
-  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters);
+                        int32_t *__restrict__ iters, const float *__restrict__ init_cv, float *__restrict__ final_cv) {
+  plain_decode_body<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, ws, hard, post, iters, init_cv, final_cv);
 }
 
 }  // namespace ldpc
@@ -112,7 +128,7 @@ size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch) {
 namespace {
 
 using PlainKernel = void (*)(GraphDev, const float *, const double *, int, int, int, char *, uint8_t *, float *,
-                             int32_t *);
+                             int32_t *, const float *, float *);
 
 template <int DC, int DV>
 PlainKernel plain_kernel_for() {
@@ -134,7 +150,8 @@ PlainKernel pick_plain(const ldpc_graph_s *g) {
 
 ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch,
                                 int32_t max_iters, int32_t early_stop, uint8_t *hard, float *post, int32_t *iters,
-                                void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream) {
+                                void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream, const float *init_cv,
+                                float *final_cv) {
   (void)ws_bytes;
   GraphDev d = graph_dev(g);
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
@@ -142,7 +159,7 @@ ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr
   const float *l32 = llr_f64 ? nullptr : (const float *)llr;
   const double *l64 = llr_f64 ? (const double *)llr : nullptr;
   hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * waves), 0, stream, d, l32, l64, (int)batch, (int)max_iters,
-                     (int)(early_stop != 0), (char *)ws, hard, post, iters);
+                     (int)(early_stop != 0), (char *)ws, hard, post, iters, init_cv, final_cv);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;
 }

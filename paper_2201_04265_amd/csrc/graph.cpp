@@ -212,7 +212,8 @@ extern "C" ldpc_status ldpc_decode_workspace_size(ldpc_graph_t g, int32_t batch,
 
 static ldpc_status decode_common(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
                                  int32_t early_stop, uint32_t flags, uint8_t *hard, float *post, int32_t *iters,
-                                 void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream) {
+                                 void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream,
+                                 const float *init_cv = nullptr, float *final_cv = nullptr) {
   if (!g) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
   if (batch < 0) return set_error(LDPC_ERR_INVALID_ARG, "batch < 0");
   if (max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "max_iters < 0");
@@ -223,7 +224,7 @@ static ldpc_status decode_common(ldpc_graph_t g, const void *llr, int32_t batch,
   if (((uintptr_t)ws & 255) != 0) return set_error(LDPC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (ws_bytes < plain_workspace_bytes(g, batch)) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small");
   return launch_plain_decode(g, llr, (flags & LDPC_LLR_F64) != 0, batch, max_iters, early_stop, hard, post, iters,
-                             ws, ws_bytes, waves, stream);
+                             ws, ws_bytes, waves, stream, init_cv, final_cv);
 }
 
 extern "C" ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
@@ -241,4 +242,14 @@ extern "C" ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32
                                           hipStream_t stream) {
   return decode_common(g, llr, batch, max_iters, early_stop, flags, hard_bits, posterior, iters_used, workspace,
                        ws_bytes, waves, stream);
+}
+
+extern "C" ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
+                                      int32_t early_stop, uint32_t flags, const float *init_cv, float *final_cv,
+                                      uint8_t *hard_bits, float *posterior, int32_t *iters_used, void *workspace,
+                                      size_t ws_bytes, hipStream_t stream) {
+  if (g && g->nnz == 0 && (init_cv || final_cv))
+    return set_error(LDPC_ERR_INVALID_ARG, "a graph without edges has no c->v state");
+  return decode_common(g, llr, batch, max_iters, early_stop, flags, hard_bits, posterior, iters_used, workspace,
+                       ws_bytes, 16, stream, init_cv, final_cv);
 }

@@ -137,7 +137,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Plain decode launcher (decode.hip).
 ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch,
                                 int32_t max_iters, int32_t early_stop, uint8_t *hard, float *post, int32_t *iters,
-                                void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream);
+                                void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream,
+                                const float *init_cv = nullptr, float *final_cv = nullptr);
 // Stream form (stream.hip): readiness of a graph for it (device facts cached; an error
 // if its word state exceeds LDS) and one enqueued decode using `counter` (device int).
 ldpc_status stream_ready_for(ldpc_graph_s *g, int32_t threads);

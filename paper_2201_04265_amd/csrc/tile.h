@@ -86,12 +86,50 @@ __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__re
   }
 }
 
+// Caller c->v state [B][nnz] (CSR edge order) -> dst [nnz][64] of the tile, through the
+// same 64 x 64 LDS blocks as the LLRs.  Lanes past the batch get zeros.
+__device__ __forceinline__ void ingest_edges(const GraphDev &g, const float *__restrict__ src, int cw0, int nvalid,
+                                             float *__restrict__ dst, float (*stage)[TW + 1], int wave, int W,
+                                             int lane) {
+  const int nnz = g.nnz;
+  for (int e0 = 0; e0 < nnz; e0 += TW) {
+    for (int r = wave; r < TW; r += W) {
+      const int e = e0 + lane;
+      stage[r][lane] = (r < nvalid && e < nnz) ? src[(size_t)(cw0 + r) * (size_t)nnz + (size_t)e] : 0.0f;
+    }
+    __syncthreads();
+    for (int q = wave; q < TW && e0 + q < nnz; q += W) dst[(e0 + q) * TW + lane] = stage[lane][q];
+    __syncthreads();
+  }
+}
+
+// Each lane's c->v messages of its last iteration (E[my_iters & 1]; zeros for a word that
+// stopped at 0 without a starting state) -> dst [B][nnz].
+__device__ __forceinline__ void egress_edges(const GraphDev &g, TileState st, int my_iters, bool from_state,
+                                             int cw0, int nvalid, float *__restrict__ dst, float (*stage)[TW + 1],
+                                             int wave, int W, int lane) {
+  const int nnz = g.nnz;
+  const float *Eb = (my_iters & 1) ? st.E1 : st.E0;
+  const bool zero = my_iters == 0 && !from_state;
+  for (int e0 = 0; e0 < nnz; e0 += TW) {
+    for (int q = wave; q < TW && e0 + q < nnz; q += W) stage[q][lane] = zero ? 0.0f : Eb[(e0 + q) * TW + lane];
+    __syncthreads();
+    for (int r = wave; r < nvalid; r += W) {
+      const int e = e0 + lane;
+      if (e < nnz) dst[(size_t)(cw0 + r) * (size_t)nnz + (size_t)e] = stage[lane][r];
+    }
+    __syncthreads();
+  }
+}
+
 // Final posterior of each lane's word from its own E buffer -> post and hard [B][n].
+// from_state: the decode started from a given c->v state in E0, so a word that stopped
+// at iteration 0 returns the posterior of that state (Eq. 7) instead of R.
 template <int DV>
 __device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int my_iters, int cw0, int nvalid,
                                             float *__restrict__ post, uint8_t *__restrict__ hard,
                                             float (*stage)[TW + 1], int wave, int W, int lane, int chunk0 = 0,
-                                            int chunk_step = 1) {
+                                            int chunk_step = 1, bool from_state = false) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
   const int n = g.n;
   const float *Eb = (my_iters & 1) ? st.E1 : st.E0;
@@ -104,7 +142,7 @@ __device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int
       int eid[DMAX];
       const float r = st.R[v * TW + lane];
       const float L = var_posterior<DV>(r, Eb, g.var_edges, p0, dv, lane, ev, pre, eid);
-      stage[q][lane] = my_iters > 0 ? L : r;
+      stage[q][lane] = (my_iters > 0 || from_state) ? L : r;
     }
     __syncthreads();
     for (int r = wave; r < nvalid; r += W) {

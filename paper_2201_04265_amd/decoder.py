@@ -54,6 +54,37 @@ def decode(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = T
     return hard, post, iters
 
 
+def decode_ex(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bool = True,
+              init_cv: torch.Tensor | None = None, want_final: bool = True, stream=None):
+    """ldpc_decode_ex: decode from the c->v state init_cv [B, edges] (float32, CSR edge order;
+    None = zeros).  Returns (hard, posterior, iters, final_cv [B, edges] or None)."""
+    if not llr.is_cuda or llr.dim() != 2 or llr.shape[1] != graph.n:
+        raise ValueError("llr must be a cuda tensor of shape [B, n]")
+    if llr.dtype not in (torch.float32, torch.float64):
+        raise ValueError("llr must be float32 or float64")
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    f64 = llr.dtype == torch.float64
+    dev = llr.device
+    if init_cv is not None:
+        if not init_cv.is_cuda or init_cv.dtype != torch.float32 or tuple(init_cv.shape) != (B, graph.edges):
+            raise ValueError("init_cv must be a cuda float32 tensor of shape [B, edges]")
+        init_cv = init_cv.contiguous()
+    hard = torch.empty((B, graph.n), dtype=torch.uint8, device=dev)
+    post = torch.empty((B, graph.n), dtype=torch.float32, device=dev)
+    iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    final = torch.empty((B, graph.edges), dtype=torch.float32, device=dev) if want_final else None
+    need = workspace_size(graph, B, f64)
+    workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    s = ctypes.c_void_p(stream_handle(stream))
+    st = lib().ldpc_decode_ex(graph.handle, _ptr(llr), B, int(max_iters), int(bool(early_stop)),
+                              LLR_F64 if f64 else 0, _ptr(init_cv) if init_cv is not None else None,
+                              _ptr(final) if final is not None else None, _ptr(hard), _ptr(post), _ptr(iters),
+                              _ptr(workspace), workspace.numel(), s)
+    check("ldpc_decode_ex", st)
+    return hard, post, iters, final
+
+
 def stream_supported(graph: Graph) -> bool:
     nb, ok = ctypes.c_size_t(), ctypes.c_int32()
     check("ldpc_stream_lds_bytes", lib().ldpc_stream_lds_bytes(graph.handle, ctypes.byref(nb), ctypes.byref(ok)))
