@@ -16,12 +16,13 @@
  *    for this sign).  With this sign the check rule of Eq. 5 holds for every
  *    check degree.
  *  - Check rule (Eq. 5, denominator 1 - prod): E_cv = 2 atanh(prod_{v'!=v} tanh(M_v'c/2)),
- *    evaluated in FP32 in the equivalent phi form
- *    |E_cv| = phi(sum_{v'!=v} phi(|M_v'c|)), phi(x) = log((e^x+1)/(e^x-1)),
- *    with exclusive prefix/suffix sums and the sign as the parity of the others.
- *  - Variable rule (Eq. 6): M_vc = clamp(R_v + sum_{c'!=c} E_c'v, -20, 20), the
- *    exclusive sum formed from a prefix and a suffix; posterior (Eq. 7)
- *    L_v = R_v + sum_c E_cv, summed in ascending check order.
+ *    evaluated as ln(s/d) of the pair d = (A-B)/2, s = (A+B)/2 with A = prod(1+q),
+ *    B = prod(1-q), q = e^-|M| over the other messages (exclusive prefix and suffix
+ *    pairs, joined in FP64), the sign as the parity of the others.  Messages and
+ *    posteriors are stored in FP32.
+ *  - Variable rule (Eq. 6): M_vc = clamp(R_v + sum_{c'!=c} E_c'v, -20, 20); posterior
+ *    (Eq. 7) L_v = R_v + sum_c E_cv (ascending check order); both summed in FP64 and
+ *    rounded once to FP32.
  *  - Messages start at E = 0, so the first check update sees M = clamp(R).
  *  - Device pointers are device memory owned by the caller; host pointers are
  *    read during the call only.  Work is enqueued on the given HIP stream and the
@@ -120,6 +121,25 @@ ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32
                            uint32_t flags, const float *init_cv, float *final_cv, uint8_t *hard_bits,
                            float *posterior, int32_t *iters_used, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
+
+/*
+ * ldpc_decode without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * tile state lives in a fixed device array of LDPC_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.  Same arguments (minus
+ * the workspace), outputs (bit for bit), and errors as ldpc_decode, plus
+ * LDPC_ERR_INVALID_ARG when the batch's tile state (ldpc_decode_workspace_size) exceeds
+ * the array: at most floor(LDPC_NOALLOC_SCRATCH_BYTES / tile bytes) x 64 words per call
+ * (about 384 words of a (3,6) n=4096 code, 17 000 of an n=96 code).  The first call on
+ * a device looks up that device's copy of the array (hipGetSymbolAddress); no call
+ * allocates or frees memory.  Every call on a GPU uses the same array: calls that
+ * overlap on one GPU (different streams, or different threads) race and must be
+ * serialised by the caller.  The array needs no clearing between calls.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (64u << 20)
+ldpc_status ldpc_decode_noalloc(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
+                                int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
+                                int32_t *iters_used, hipStream_t stream);
 
 /* Decode with an explicit launch shape: waves per workgroup (1..16; ldpc_decode uses 16).
  * Same contract as ldpc_decode. */

@@ -49,11 +49,10 @@ __device__ __forceinline__ void egress_lanes(const GraphDev &g, TileState st, in
     int p0, dv;
     var_range<DV>(g, v, p0, dv);
     float L = st.R[v * TW + lane];
-    if (it_lane > 0) {
-      // same terms in the same order as var_posterior: R + E_0 + E_1 + ...
-#pragma unroll
-      for (int j = 0; j < DMAX; ++j)
-        if (DV > 0 || j < dv) L += Ep[g.var_edges[p0 + j] * TW + lane];
+    if (it_lane > 0) {  // the variable phase's own sum (var_posterior)
+      float ev[DMAX];
+      int eid[DMAX];
+      L = (float)var_posterior<DV>(L, Ep, g.var_edges, p0, dv, lane, ev, eid);
     }
     prow[v] = L;
     hrow[v] = L <= 0.0f ? 1 : 0;

@@ -57,25 +57,58 @@ __device__ __forceinline__ float v2c_store(float x, bool z) {
 //   one message       (d, s) = (q, 1)            the empty set (0, 1)
 //   joining two sets  (d, s) = (d1 s2 + s1 d2, s1 s2 + d1 d2)
 // so neither a tanh near 1 (large |M|, where 1 - tanh cancels) nor one near 0 loses
-// the difference A - B, and the magnitude is ln(s / d): one exp2 per message and one
-// reciprocal and one log2 per output.  The pair of the other messages of edge j joins
-// a prefix pair (messages before j) and a suffix pair (after j).  |M_i| <= 20 keeps
-// q_i >= 2e-9 and d > 0; a zero message (q = 1) gives d = s and so a zero output on
-// the others.  Error of the FP32 magnitude: below 5.5e-7 max(|E|, 1) (an absolute
-// error for small outputs, a relative one above 1).
+// the difference A - B, and the magnitude is ln(s / d).  The pair of the other messages
+// of edge j joins a prefix pair (messages before j) and a suffix pair (after j).
+// |M_i| <= 20 keeps q_i >= 2e-9 and d > 0; a zero message (q = 1) gives d = s and so a
+// zero output on the others.
 //
+// Precision (each step chosen so that a stored FP32 message carries about the error of
+// its own rounding, which loopy decoding otherwise amplifies along long trajectories):
+//  * q: the exponent |M| log2(e) is split into yh (its FP32 rounding) and the residual
+//    yl (exact from an fma, plus the constant's low part), and q = 2^-yh (1 - yl ln 2);
+//    FP32, within the hardware exp2's error (0.8 ulp) of e^-|M|.
+//  * joins: the running pairs accumulate in FP64 (full-rate FMA on this chip), so a
+//    chain of joins adds no FP32 rounding; a prefix pair is kept as FP32 d and s - 1
+//    (s - 1 is small when the messages are large, so s keeps its low digits).
+//  * output: the ratio s / d in FP64 (the hardware FP64 reciprocal refined by one
+//    Newton step), then rounded once to FP32 for the hardware log2.
 // Signs.  sign_j is the product of the other messages' signs, taken from the IEEE sign
 // bits (as the tanh product would give it, including the sign of zeros): the XOR of
 // all sign bits with M_j's own.
 // STORED: mv holds stored messages (M / 16 with a decision in bit 30, see v2c_store);
-// otherwise plain values M.  Both give the same outputs bit for bit: (M / 16) times
-// 16 log2(e) rounds exactly as M times log2(e).  Returns the XOR of the input bit
-// patterns: bit 31 is the sign of the product of all messages, and for stored
+// otherwise plain values M.  Both give the same outputs bit for bit: the exponent is
+// formed from |M| / 16 in both cases (exact), times 16 log2(e).  Returns the XOR of the
+// input bit patterns: bit 31 is the sign of the product of all messages, and for stored
 // messages bit 30 is the parity of the decisions they carry (syndrome_bit).
 // DC > 0: degree fixed at compile time; DC < 0: any degree up to -DC (runtime dc).
 // AUX: also returns, per edge, q_j = e^-|M_j| in aq and r_j = e^|E_j| (the ratio s / d
 // whose logarithm is the output magnitude) in ar, for the adjoint.
 // emit(j, E_j) receives the outputs, last edge first, after every input has been read.
+constexpr float kYHi = 23.083120346069336f;     // 16 log2(e) rounded to FP32
+constexpr float kYLo = 3.0815408536000177e-07f; // 16 log2(e) - kYHi
+
+// q = e^-|M| from x16 = |M| / 16.
+__device__ __forceinline__ float msg_q(float x16) {
+  const float yh = x16 * kYHi;
+  const float yl = fmaf(x16, kYLo, fmaf(x16, kYHi, -yh));
+  const float qh = __builtin_amdgcn_exp2f(-yh);
+  return fmaf(qh, -yl * kLn2, qh);
+}
+
+// s / d of a pair (s >= d > 0) in FP64: hardware reciprocal (~5e-8) and one Newton step.
+__device__ __forceinline__ double pair_ratio(double d, double s) {
+  const double r0 = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, r0, 1.0);
+  const double q0 = s * r0;
+  return fma(q0, e, q0);
+}
+
+// Magnitude ln(ratio) of an output; ratio >= 1 up to rounding (|log2| keeps it >= 0).
+__device__ __forceinline__ float ratio_log(double ratio, float &rf) {
+  rf = (float)ratio;
+  return fabsf(__builtin_amdgcn_logf(rf)) * kLn2;
+}
+
 template <int DC, bool STORED = false, bool AUX = false, class Emit>
 __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emit emit, float *aq = nullptr,
                                                     float *ar = nullptr) {
@@ -84,7 +117,7 @@ __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emi
   // qs[j] = q_j, and the sign of M_j: for degrees up to 16 the message's bit pattern is
   // kept (mb); above, the sign bit rides in qs[j] so that the messages need not stay live.
   constexpr bool KEEP_BITS = FIXED && DMAX <= 16;
-  float qs[DMAX], pd[DMAX], ps[DMAX];
+  float qs[DMAX], pd[DMAX], ps[DMAX];  // ps holds s - 1 of the prefix pairs
   uint32_t mb[KEEP_BITS ? DMAX : 1];
   uint32_t sx = 0;
 #pragma unroll
@@ -92,8 +125,7 @@ __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emi
     if (FIXED || j < dc) {
       const uint32_t b = __float_as_uint(mv[j]);
       sx ^= b;
-      const float q = STORED ? __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown))
-                             : __builtin_amdgcn_exp2f(-fabsf(mv[j]) * kL2e);
+      const float q = msg_q(STORED ? __uint_as_float(b & 0x3fffffffu) : fabsf(mv[j]) * kMsgDown);
       if (KEEP_BITS) {
         mb[KEEP_BITS ? j : 0] = b;
         qs[j] = q;
@@ -109,56 +141,56 @@ __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emi
   // plain product feeding an fma's addend (x * 1 rounds to x either way), never as an
   // fma multiplicand: folding fma(a, 1, b * c) to a + b * c would let the compiler fuse
   // b * c differently in the two, and fixed and generic degrees must agree bit for bit.
-  float d = 0.0f, s = 1.0f;
+  double d = 0.0, s = 1.0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      pd[j] = d;
-      ps[j] = s;
-      const float q = fabsf(qs[j]);
+      pd[j] = (float)d;
+      ps[j] = (float)(s - 1.0);
+      const double q = (double)fabsf(qs[j]);
       if (j == 0) {
         d = q;
-        s = 1.0f;
+        s = 1.0;
       } else {
-        const float dn = fmaf(s, q, d);
-        s = fmaf(d, q, s);
+        const double dn = fma(s, q, d);
+        s = fma(d, q, s);
         d = dn;
       }
     }
   }
-  d = 0.0f;
-  s = 1.0f;
+  d = 0.0;
+  s = 1.0;
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {
     if (FIXED || j < dc) {
       const bool top = FIXED && j == DMAX - 1;  // empty suffix
-      float od, os;
+      double od, os;
       if (j == 0) {
         od = d;
         os = s;
       } else if (top) {
-        od = pd[j];
-        os = ps[j];
+        od = (double)pd[j];
+        os = 1.0 + (double)ps[j];
       } else {
-        od = fmaf(ps[j], d, pd[j] * s);
-        os = fmaf(pd[j], d, ps[j] * s);
+        const double pdj = (double)pd[j], psj = 1.0 + (double)ps[j];
+        od = fma(psj, d, pdj * s);
+        os = fma(pdj, d, psj * s);
       }
-      // |log2|: rounding can put os / od a hair below 1 when the exact output is ~1e-7
-      const float ratio = os * __builtin_amdgcn_rcpf(od);
-      const float mag = fabsf(__builtin_amdgcn_logf(ratio)) * kLn2;
+      float rf;
+      const float mag = ratio_log(pair_ratio(od, os), rf);
       if (AUX) {
         aq[j] = fabsf(qs[j]);
-        ar[j] = fmaxf(ratio, 1.0f);
+        ar[j] = fmaxf(rf, 1.0f);
       }
       const uint32_t sgn = (sx ^ (KEEP_BITS ? mb[KEEP_BITS ? j : 0] : __float_as_uint(qs[j]))) & 0x80000000u;
       emit(j, __uint_as_float(sgn | __float_as_uint(mag)));
-      const float q = fabsf(qs[j]);
+      const double q = (double)fabsf(qs[j]);
       if (top) {
         d = q;
-        s = 1.0f;
+        s = 1.0;
       } else {
-        const float dn = fmaf(s, q, d);
-        s = fmaf(d, q, s);
+        const double dn = fma(s, q, d);
+        s = fma(d, q, s);
         d = dn;
       }
     }
@@ -175,8 +207,8 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
 
 // check_core for a runtime degree (DC < 0) on stored messages, in place on the check's
 // own LDS row: the row holds the inputs, then (while the prefix pairs are formed) the
-// second halves of the prefix pairs, then the outputs.  Each row entry is read back
-// before it is overwritten by the same thread.  The arithmetic and its order are
+// second halves of the prefix pairs (s - 1), then the outputs.  Each row entry is read
+// back before it is overwritten by the same thread.  The arithmetic and its order are
 // those of check_core<DC, true>, so the outputs are the same bit for bit; the row
 // stands in for one of the three register arrays of -DC values.  Entry j of the row
 // is row[j * STRIDE] (64 when the 64 checks of a wavefront interleave their rows).
@@ -191,50 +223,51 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
     if (j < dc) {
       const uint32_t b = __float_as_uint(row[j * STRIDE]);
       sx ^= b;
-      const float q = __builtin_amdgcn_exp2f(-__uint_as_float(b & 0x3fffffffu) * (kL2e / kMsgDown));
+      const float q = msg_q(__uint_as_float(b & 0x3fffffffu));
       qs[j] = __uint_as_float(__float_as_uint(q) | (b & 0x80000000u));
     }
   }
-  float d = 0.0f, s = 1.0f;
+  double d = 0.0, s = 1.0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (j < dc) {
-      pd[j] = d;
-      row[j * STRIDE] = s;
-      const float q = fabsf(qs[j]);
+      pd[j] = (float)d;
+      row[j * STRIDE] = (float)(s - 1.0);
+      const double q = (double)fabsf(qs[j]);
       if (j == 0) {
         d = q;
-        s = 1.0f;
+        s = 1.0;
       } else {
-        const float dn = fmaf(s, q, d);
-        s = fmaf(d, q, s);
+        const double dn = fma(s, q, d);
+        s = fma(d, q, s);
         d = dn;
       }
     }
   }
-  d = 0.0f;
-  s = 1.0f;
+  d = 0.0;
+  s = 1.0;
 #pragma unroll
   for (int j = DMAX - 1; j >= 0; --j) {
     if (j < dc) {
-      float od, os;
+      double od, os;
       if (j == 0) {
         od = d;
         os = s;
       } else {
         // after one element the second half is exactly 1: written as the literal, as it
         // is a constant in check_core, so that the compiler forms the same operations
-        const float psj = j == 1 ? 1.0f : row[j * STRIDE];
-        od = fmaf(psj, d, pd[j] * s);
-        os = fmaf(pd[j], d, psj * s);
+        const double psj = j == 1 ? 1.0 : 1.0 + (double)row[j * STRIDE];
+        const double pdj = (double)pd[j];
+        od = fma(psj, d, pdj * s);
+        os = fma(pdj, d, psj * s);
       }
-      const float ratio = os * __builtin_amdgcn_rcpf(od);
-      const float mag = fabsf(__builtin_amdgcn_logf(ratio)) * kLn2;
+      float rf;
+      const float mag = ratio_log(pair_ratio(od, os), rf);
       const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
       row[j * STRIDE] = __uint_as_float(sgn | __float_as_uint(mag));
-      const float q = fabsf(qs[j]);
-      const float dn = fmaf(s, q, d);
-      s = fmaf(d, q, s);
+      const double q = (double)fabsf(qs[j]);
+      const double dn = fma(s, q, d);
+      s = fma(d, q, s);
       d = dn;
     }
   }
@@ -278,42 +311,42 @@ __device__ __forceinline__ int check_update(const float *__restrict__ Mt, float 
                                             int lane, bool store) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
-  float mv[DMAX], ev[DMAX];
+  float mv[DMAX];
 #pragma unroll
   for (int j = 0; j < DMAX; ++j)
     if (FIXED || j < dc) mv[j] = Mt[(e0 + j) * TW + lane];
-  const uint32_t sx = check_core<DC, true>(mv, dc, ev);
-#pragma unroll
-  for (int j = 0; j < DMAX; ++j)
-    if ((FIXED || j < dc) && store) Et[(e0 + j) * TW + lane] = ev[j];
+  // outputs go straight to Et (every input has been read by then): no output array
+  const uint32_t sx = check_core_emit<DC, true>(mv, dc, [&](int j, float v) {
+    if (store) Et[(e0 + j) * TW + lane] = v;
+  });
   return syndrome_bit(sx);
 }
 
-// Exclusive sums of Eq. 6 as prefix + suffix: emit(j, pre[j] + sum_{i > j} ev[i]), where
-// pre[j] = R_v + sum_{i < j} ev[i].  The last message's suffix is empty and adds nothing
-// (emit gets pre exactly).  DV as DC above; every form of the decoder uses this order.
-template <int DV, typename Emit>
-__device__ __forceinline__ void var_exclusive(const float *pre, const float *ev, int dv, Emit &&emit) {
+// Variable-node sums (Eqs. 6-7) in FP64: the posterior L = R_v + sum_i x_i (ascending
+// check order) and the extrinsic sums L - x_j, each rounded once to FP32 where it is
+// stored.  In FP64 the total-minus-own form loses nothing at FP32 output precision (its
+// error is ~1e-16 |L|), and one rounding per stored value instead of a chain of FP32
+// additions keeps the per-iteration error near that of correct rounding.  DV as DC above;
+// every form of the decoder uses these two functions.
+template <int DV>
+__device__ __forceinline__ double var_total(float r, const float *x, int dv) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
-  constexpr bool FIXED = DV > 0;
-  float suf = 0.0f;
+  double L = (double)r;
 #pragma unroll
-  for (int j = DMAX - 1; j >= 0; --j) {
-    if (FIXED || j < dv) {
-      const bool last = FIXED ? j == DMAX - 1 : j == dv - 1;
-      emit(j, last ? pre[j] : pre[j] + suf);
-      suf = last ? ev[j] : suf + ev[j];
-    }
-  }
+  for (int j = 0; j < DMAX; ++j)
+    if (DV > 0 || j < dv) L += (double)x[j];
+  return L;
 }
 
-// Posterior of one variable (Eq. 7): R_v + the incoming c->v messages in ascending
-// check order.  Also returns the running prefixes pre[j] = R_v + sum_{i<j} E_i and
-// the messages themselves for the exclusive sums of Eq. 6.  DV as DC above.
+// Extrinsic sum of message j from the FP64 total, rounded once (pre-clamp).
+__device__ __forceinline__ float var_extrinsic(double L, float xj) { return (float)(L - (double)xj); }
+
+// Posterior of one variable (Eq. 7), FP64, from the incoming c->v messages of tile
+// buffer Et; also returns the messages and their edge ids.  DV as DC above.
 template <int DV>
-__device__ __forceinline__ float var_posterior(float r, const float *__restrict__ Et,
-                                               const int32_t *__restrict__ var_edges, int p0, int dv, int lane,
-                                               float *ev, float *pre, int *eid) {
+__device__ __forceinline__ double var_posterior(float r, const float *__restrict__ Et,
+                                                const int32_t *__restrict__ var_edges, int p0, int dv, int lane,
+                                                float *ev, int *eid) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
   constexpr bool FIXED = DV > 0;
 #pragma unroll
@@ -323,19 +356,11 @@ __device__ __forceinline__ float var_posterior(float r, const float *__restrict_
       ev[j] = Et[eid[j] * TW + lane];
     }
   }
-  float acc = r;
-#pragma unroll
-  for (int j = 0; j < DMAX; ++j) {
-    if (FIXED || j < dv) {
-      pre[j] = acc;
-      acc += ev[j];
-    }
-  }
-  return acc;
+  return var_total<DV>(r, ev, dv);
 }
 
-// Variable-node update: posterior L (Eq. 7), its decision z = [L <= 0] (Eq. 8), and
-// the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6) as prefix + suffix,
+// Variable-node update: posterior L (Eq. 7), its decision z = [L <= 0] (Eq. 8, on the
+// FP32 posterior), and the v->c messages M_j = clamp(R_v + sum_{i != j} E_i) (Eq. 6),
 // stored carrying z.  With ZERO_E, lanes with `fresh` set see all incoming messages as 0
 // (a word that has not been through a check phase yet): M = clamp(R), z = [R <= 0].
 template <int DV, bool ZERO_E = false>
@@ -343,21 +368,21 @@ __device__ __forceinline__ void var_update(const float *__restrict__ Rt, const f
                                            float *__restrict__ Mt, const int32_t *__restrict__ var_edges, int p0,
                                            int dv, int v, int lane, bool store, bool fresh = false) {
   constexpr int DMAX = DV > 0 ? DV : -DV;
-  float ev[DMAX], pre[DMAX];
+  float ev[DMAX];
   int eid[DMAX];
   const float r = Rt[v * TW + lane];
-  float L = var_posterior<DV>(r, Et, var_edges, p0, dv, lane, ev, pre, eid);
+  double L = var_posterior<DV>(r, Et, var_edges, p0, dv, lane, ev, eid);
   if (ZERO_E && fresh) {
 #pragma unroll
-    for (int j = 0; j < DMAX; ++j) {
-      ev[j] = 0.0f;
-      pre[j] = r;
-    }
-    L = r;
+    for (int j = 0; j < DMAX; ++j) ev[j] = 0.0f;
+    L = (double)r;
   }
-  const bool z = L <= 0.0f;
-  if (store)
-    var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { Mt[eid[j] * TW + lane] = v2c_store(x, z); });
+  const bool z = (float)L <= 0.0f;
+  if (store) {
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j)
+      if (DV > 0 || j < dv) Mt[eid[j] * TW + lane] = v2c_store(var_extrinsic(L, ev[j]), z);
+  }
 }
 
 }  // namespace ldpc

@@ -144,21 +144,17 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       // and an edge's byte offset is its LDS address.
       auto xat = [](int off) { return (__attribute__((address_space(3))) float *)(size_t)off; };
       auto update_dv = [&](int v, const VarIn &f, int dv) __attribute__((always_inline)) {
-        float ev[DVM], pre[DVM];
+        float ev[DVM];
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
           if (DV > 0 || j < dv) ev[j] = *xat(f.off[j]);
-        float acc = f.r;
+        const double L = var_total<DV>(f.r, ev, dv);
+        const float Lf = (float)L;
+        *(float *)((char *)prow + (uint32_t)v * 4u) = Lf;
+        const bool z = Lf <= 0.0f;
 #pragma unroll
-        for (int j = 0; j < DVM; ++j) {
-          if (DV > 0 || j < dv) {
-            pre[j] = acc;
-            acc += ev[j];
-          }
-        }
-        *(float *)((char *)prow + (uint32_t)v * 4u) = acc;
-        const bool z = acc <= 0.0f;
-        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { *xat(f.off[j]) = v2c_store(x, z); });
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dv) *xat(f.off[j]) = v2c_store(var_extrinsic(L, ev[j]), z);
       };
       auto update = [&](int v, const VarIn &f) {
         if constexpr (DV > 0) {

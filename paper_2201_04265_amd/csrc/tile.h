@@ -138,10 +138,10 @@ __device__ __forceinline__ void egress_tile(const GraphDev &g, TileState st, int
       const int v = v0 + q;
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      float ev[DMAX], pre[DMAX];
+      float ev[DMAX];
       int eid[DMAX];
       const float r = st.R[v * TW + lane];
-      const float L = var_posterior<DV>(r, Eb, g.var_edges, p0, dv, lane, ev, pre, eid);
+      const float L = (float)var_posterior<DV>(r, Eb, g.var_edges, p0, dv, lane, ev, eid);
       stage[q][lane] = (my_iters > 0 || from_state) ? L : r;
     }
     __syncthreads();

@@ -178,28 +178,24 @@ __global__ void __launch_bounds__(512)
     for (int v = wave; v < g.n; v += W) {
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      float ev[DVM], pre[DVM];
+      double x[DVM];
       int eid[DVM];
       const float r = st.R[v * TW + lane];
+      double L = (double)r;  // the plain decoder's FP64 sums (var_total) over weighted messages
 #pragma unroll
       for (int j = 0; j < DVM; ++j) {
         if (DV > 0 || j < dv) {
           eid[j] = g.var_edges[p0 + j];
-          ev[j] = wt[eid[j]] * st.E[eid[j] * TW + lane];
-        }
-      }
-      float acc = r;
-#pragma unroll
-      for (int j = 0; j < DVM; ++j) {
-        if (DV > 0 || j < dv) {
-          pre[j] = acc;
-          acc += ev[j];
+          x[j] = (double)wt[eid[j]] * (double)st.E[eid[j] * TW + lane];  // exact product
+          L += x[j];
         }
       }
       if (t < T) {
-        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { An[eid[j] * TW + lane] = x; });
+#pragma unroll
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dv) An[eid[j] * TW + lane] = (float)(L - x[j]);
       } else {
-        st.R[v * TW + lane] = acc;  // posterior replaces R after the last iteration
+        st.R[v * TW + lane] = (float)L;  // posterior replaces R after the last iteration
       }
     }
     __syncthreads();
@@ -374,27 +370,24 @@ __global__ void __launch_bounds__(512)
     for (int v = tid; v < g.n; v += NT) {
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
-      float ev[DVM], pre[DVM];
+      double x[DVM];
       int eid[DVM];
+      double L = (double)R[v];  // the plain decoder's FP64 sums (var_total) over weighted messages
 #pragma unroll
       for (int j = 0; j < DVM; ++j) {
         if (DV > 0 || j < dv) {
           eid[j] = g.var_edges[p0 + j];
-          ev[j] = (STAGE_W ? Wl[eid[j]] : wt[eid[j]]) * X[eid[j]];
+          x[j] = (double)(STAGE_W ? Wl[eid[j]] : wt[eid[j]]) * (double)X[eid[j]];  // exact product
+          L += x[j];
         }
       }
-      float acc = R[v];
+      if (t < T) {
 #pragma unroll
-      for (int j = 0; j < DVM; ++j) {
-        if (DV > 0 || j < dv) {
-          pre[j] = acc;
-          acc += ev[j];
-        }
+        for (int j = 0; j < DVM; ++j)
+          if (DV > 0 || j < dv) X[eid[j]] = (float)(L - x[j]);
+      } else {
+        out[v] = (float)L;
       }
-      if (t < T)
-        var_exclusive<DV>(pre, ev, dv, [&](int j, float x) { X[eid[j]] = x; });
-      else
-        out[v] = acc;
     }
     lds_barrier();
   }
