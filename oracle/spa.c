@@ -265,9 +265,11 @@ static int run_jobs(job_t *proto, int64_t B, int32_t nthreads) {
   if (nthreads > B) nthreads = (int32_t)(B > 0 ? B : 1);
   job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
   pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
-  if (!jobs || !th) {
+  char *created = (char *)calloc((size_t)nthreads, 1); /* read and written by this thread only */
+  if (!jobs || !th || !created) {
     free(jobs);
     free(th);
+    free(created);
     return -1;
   }
   /* Eq. 9 block split: worker x gets floor(B/N) + [x < B mod N] consecutive words */
@@ -280,18 +282,18 @@ static int run_jobs(job_t *proto, int64_t B, int32_t nthreads) {
     start += cnt;
   }
   int rc = 0;
-  for (int32_t x = 1; x < nthreads; x++)
-    if (pthread_create(&th[x], NULL, worker, &jobs[x])) {
-      jobs[x].status = -2;
-      worker(&jobs[x]);
-    }
+  for (int32_t x = 1; x < nthreads; x++) {
+    created[x] = pthread_create(&th[x], NULL, worker, &jobs[x]) == 0;
+    if (!created[x]) worker(&jobs[x]); /* no thread: this one does the share */
+  }
   worker(&jobs[0]);
   for (int32_t x = 1; x < nthreads; x++)
-    if (jobs[x].status != -2) pthread_join(th[x], NULL);
-  for (int32_t x = 0; x < nthreads; x++)
+    if (created[x]) pthread_join(th[x], NULL);
+  for (int32_t x = 0; x < nthreads; x++) /* every worker has finished: statuses are final */
     if (jobs[x].status == -1) rc = -1;
   free(jobs);
   free(th);
+  free(created);
   return rc;
 }
 

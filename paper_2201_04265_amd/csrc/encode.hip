@@ -339,45 +339,6 @@ ldpc_status launch_encode(const ldpc_encoder_s *e, const uint8_t *msg_in, int32_
   return LDPC_OK;
 }
 
-// Reduced row echelon form of H over GF(2), pivots from the last column down.
-void systematic_form(const ldpc_graph_s *g, std::vector<int32_t> &pivots, std::vector<uint64_t> &rows, int &W) {
-  const int m = g->m, n = g->n;
-  W = (n + 63) / 64;
-  rows.assign((size_t)m * W, 0);
-  for (int c = 0; c < m; ++c)
-    for (int32_t p = g->row_ptr[c]; p < g->row_ptr[c + 1]; ++p) {
-      const int v = g->col_idx[p];
-      rows[(size_t)c * W + (v >> 6)] |= 1ull << (v & 63);
-    }
-  int rank = 0;
-  pivots.clear();
-  for (int col = n - 1; col >= 0 && rank < m; --col) {
-    const int cw = col >> 6;
-    const uint64_t cb = 1ull << (col & 63);
-    int p = -1;
-    for (int r = rank; r < m; ++r)
-      if (rows[(size_t)r * W + cw] & cb) {
-        p = r;
-        break;
-      }
-    if (p < 0) continue;
-    if (p != rank)
-      std::swap_ranges(rows.begin() + (size_t)p * W, rows.begin() + (size_t)(p + 1) * W,
-                       rows.begin() + (size_t)rank * W);
-    // the pivot row is zero right of col (earlier pivots eliminated, skipped columns
-    // are zero in every remaining row), so only words 0..cw change
-    const uint64_t *pr = &rows[(size_t)rank * W];
-    for (int r = 0; r < m; ++r) {
-      if (r == rank) continue;
-      uint64_t *rr = &rows[(size_t)r * W];
-      if (rr[cw] & cb)
-        for (int x = 0; x <= cw; ++x) rr[x] ^= pr[x];
-    }
-    pivots.push_back(col);
-    ++rank;
-  }
-}
-
 }  // namespace
 
 extern "C" ldpc_status ldpc_encoder_create(ldpc_graph_t g, ldpc_encoder_t *out) {

@@ -66,43 +66,6 @@ ldpc_status upload(const std::vector<int32_t> &h, int32_t **d) {
   return LDPC_OK;
 }
 
-// Validate the compressed arrays and produce CSR with sorted rows.
-ldpc_status build_csr(int32_t m, int32_t n, ldpc_format fmt, const int32_t *ptr, const int32_t *idx, int64_t nnz,
-                      std::vector<int32_t> &row_ptr, std::vector<int32_t> &col_idx) {
-  const int32_t outer = fmt == LDPC_CSR ? m : n;
-  const int32_t inner = fmt == LDPC_CSR ? n : m;
-  if (ptr[0] != 0) return set_error(LDPC_ERR_BAD_MATRIX, "ptr[0] must be 0");
-  for (int32_t i = 0; i < outer; i++)
-    if (ptr[i + 1] < ptr[i]) return set_error(LDPC_ERR_BAD_MATRIX, "ptr is not non-decreasing");
-  if ((int64_t)ptr[outer] != nnz) return set_error(LDPC_ERR_BAD_MATRIX, "ptr[last] != nnz");
-  for (int64_t k = 0; k < nnz; k++)
-    if (idx[k] < 0 || idx[k] >= inner) return set_error(LDPC_ERR_BAD_MATRIX, "index out of range");
-  // counting sort into CSR; rows sorted by variable
-  std::vector<int64_t> cnt((size_t)m + 1, 0);
-  if (fmt == LDPC_CSR) {
-    for (int32_t c = 0; c < m; c++) cnt[c + 1] = ptr[c + 1] - ptr[c];
-  } else {
-    for (int64_t k = 0; k < nnz; k++) cnt[idx[k] + 1]++;
-  }
-  for (int32_t c = 0; c < m; c++) cnt[c + 1] += cnt[c];
-  row_ptr.assign((size_t)m + 1, 0);
-  for (int32_t c = 0; c <= m; c++) row_ptr[c] = (int32_t)cnt[c];
-  col_idx.assign((size_t)nnz, 0);
-  if (fmt == LDPC_CSR) {
-    std::memcpy(col_idx.data(), idx, (size_t)nnz * sizeof(int32_t));
-  } else {
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int32_t v = 0; v < n; v++)
-      for (int32_t k = ptr[v]; k < ptr[v + 1]; k++) col_idx[fill[idx[k]]++] = v;
-  }
-  for (int32_t c = 0; c < m; c++) {
-    auto b = col_idx.begin() + row_ptr[c], e = col_idx.begin() + row_ptr[c + 1];
-    std::sort(b, e);
-    if (std::adjacent_find(b, e) != e) return set_error(LDPC_ERR_BAD_MATRIX, "repeated entry in H");
-  }
-  return LDPC_OK;
-}
-
 }  // namespace
 
 extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, ldpc_format fmt, const int32_t *ptr,
@@ -112,53 +75,17 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, ldpc_format fmt, 
   if (fmt != LDPC_CSR && fmt != LDPC_CSC) return set_error(LDPC_ERR_INVALID_ARG, "unknown format");
   if (m <= 0 || n <= 0) return set_error(LDPC_ERR_BAD_MATRIX, "m and n must be positive");
   if (nnz < 0 || nnz > INT32_MAX) return set_error(LDPC_ERR_BAD_MATRIX, "nnz out of range");
-  if (!ptr || (nnz > 0 && !idx)) return set_error(LDPC_ERR_INVALID_ARG, "ptr/idx is NULL");
-
   ldpc_graph_s *g = new (std::nothrow) ldpc_graph_s();
   if (!g) return set_error(LDPC_ERR_OUT_OF_MEMORY, "graph allocation");
-  g->m = m;
-  g->n = n;
-  g->nnz = nnz;
-  ldpc_status st = build_csr(m, n, fmt, ptr, idx, nnz, g->row_ptr, g->col_idx);
+  if (!ptr || (nnz > 0 && !idx)) {
+    delete g;
+    return set_error(LDPC_ERR_INVALID_ARG, "ptr/idx is NULL");
+  }
+  std::string err;
+  ldpc_status st = graph_build_host(m, n, fmt, ptr, idx, nnz, *g, err);
   if (st != LDPC_OK) {
     delete g;
-    return st;
-  }
-  g->dc_min = INT32_MAX;
-  g->dc_max = 0;
-  g->chk_of_edge.resize((size_t)nnz);
-  for (int32_t c = 0; c < m; c++) {
-    int32_t d = g->row_ptr[c + 1] - g->row_ptr[c];
-    g->dc_min = std::min(g->dc_min, d);
-    g->dc_max = std::max(g->dc_max, d);
-    for (int32_t e = g->row_ptr[c]; e < g->row_ptr[c + 1]; e++) g->chk_of_edge[e] = c;
-  }
-  if (g->dc_min < 2) {
-    delete g;
-    return set_error(LDPC_ERR_BAD_MATRIX, "every check needs degree >= 2");
-  }
-  g->var_ptr.assign((size_t)n + 1, 0);
-  for (int64_t e = 0; e < nnz; e++) g->var_ptr[g->col_idx[e] + 1]++;
-  g->dv_min = INT32_MAX;
-  g->dv_max = 0;
-  for (int32_t v = 0; v < n; v++) {
-    g->dv_min = std::min(g->dv_min, g->var_ptr[v + 1]);
-    g->dv_max = std::max(g->dv_max, g->var_ptr[v + 1]);
-    g->var_ptr[v + 1] += g->var_ptr[v];
-  }
-  g->var_edges.assign((size_t)nnz, 0);
-  {
-    std::vector<int32_t> fill(g->var_ptr.begin(), g->var_ptr.end() - 1);
-    for (int64_t e = 0; e < nnz; e++) g->var_edges[fill[g->col_idx[e]]++] = (int32_t)e;
-  }
-  if (g->dc_max > LDPC_MAX_CHECK_DEGREE || g->dv_max > LDPC_MAX_VAR_DEGREE) {
-    delete g;
-    return set_error(LDPC_ERR_UNSUPPORTED, "check degree > " + std::to_string(LDPC_MAX_CHECK_DEGREE) +
-                                               " or variable degree > " + std::to_string(LDPC_MAX_VAR_DEGREE));
-  }
-  if ((int64_t)n * kTile > INT32_MAX || nnz * kTile > INT32_MAX) {
-    delete g;
-    return set_error(LDPC_ERR_UNSUPPORTED, "graph too large for 32-bit per-tile offsets");
+    return set_error(st, err);
   }
   g->stream_x_floats = stream_x_floats(g);
   hipError_t e = hipGetDevice(&g->device);

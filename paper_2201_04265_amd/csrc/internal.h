@@ -9,15 +9,10 @@
 #include <vector>
 
 #include "../../include/ldpc.h"
+#include "host_layout.h"
 
-// Tanner graph: host arrays plus device copies.  Edge e (CSR order) joins
-// check chk_of_edge[e] and variable col_idx[e]; var_edges lists, for each
-// variable, its edge ids in ascending order (= ascending check index).
-struct ldpc_graph_s {
-  int32_t m = 0, n = 0;
-  int64_t nnz = 0;
-  int32_t dc_min = 0, dc_max = 0, dv_min = 0, dv_max = 0;
-  std::vector<int32_t> row_ptr, col_idx, chk_of_edge, var_ptr, var_edges;
+// Tanner graph: the host arrays (GraphHost) plus device copies.
+struct ldpc_graph_s : GraphHost {
   int device = 0;
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_var_ptr = nullptr, *d_var_edges = nullptr;
   int32_t *d_var_xoff = nullptr;  // stream form: LDS byte offsets of the edges (var_edges order)
@@ -43,8 +38,6 @@ struct ldpc_encoder_s {
   int32_t *d_colmap = nullptr;            // [n]: message index j, or -1 - r for the pivot of row r
 };
 
-// Floats of the stream form's per-word message array for this graph's layout (stream.hip).
-int64_t stream_x_floats(const ldpc_graph_s *g);
 
 // Device view passed to kernels by value.
 struct GraphDev {
@@ -72,39 +65,6 @@ inline GraphDev graph_dev(const ldpc_graph_s *g) {
   return d;
 }
 
-// Degree specialisations compiled for the kernels: fixed (dc, dv) pairs, then
-// generic kernels for irregular codes up to a maximum check degree.
-enum KernelKind : int32_t {
-  KIND_6_3 = 0,
-  KIND_4_3,
-  KIND_12_3,
-  KIND_15_3,
-  KIND_12_6,
-  KIND_12_9,
-  KIND_G8,
-  KIND_G16,
-  KIND_G24,
-  KIND_G32,
-  KIND_COUNT
-};
-
-inline int32_t kernel_kind(const ldpc_graph_s *g) {
-  const bool reg = g->dc_min == g->dc_max && g->dv_min == g->dv_max;
-  if (reg) {
-    const int dc = g->dc_max, dv = g->dv_max;
-    if (dc == 6 && dv == 3) return KIND_6_3;
-    if (dc == 4 && dv == 3) return KIND_4_3;
-    if (dc == 12 && dv == 3) return KIND_12_3;
-    if (dc == 15 && dv == 3) return KIND_15_3;
-    if (dc == 12 && dv == 6) return KIND_12_6;
-    if (dc == 12 && dv == 9) return KIND_12_9;
-  }
-  if (g->dc_max <= 8) return KIND_G8;
-  if (g->dc_max <= 16) return KIND_G16;
-  if (g->dc_max <= 24) return KIND_G24;
-  return KIND_G32;
-}
-
 // Expands F(DC, DV) for the specialisation of `kind` (DC/DV < 0: generic up to -DC/-DV).
 #define LDPC_KIND_SWITCH(kind, F)                         \
   switch (kind) {                                         \
@@ -130,7 +90,6 @@ ldpc_status hip_error(hipError_t e, const char *what);
     if (e_ != hipSuccess) return hip_error(e_, #call);     \
   } while (0)
 
-constexpr int kTile = 64;  // codewords per tile: one per wavefront lane
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -279,134 +279,6 @@ int stream_threads(const ldpc_graph_s *g, int max_threads, int32_t batch) {
   return best_nt;
 }
 
-// Runtime check degrees: the checks, sorted by degree (ties in index order), are dealt
-// in groups of 64, one group per wavefront pass of the check phase.  Group i starts at
-// float start_i and holds entry j of its l-th check at start_i + 64 j + l, so the 64
-// lanes of a wavefront read and write 64 consecutive floats (64 distinct LDS banks).
-// A group spans 64 x its largest degree floats (the last one only up to its last
-// entry); when every group has one degree (quasi-cyclic codes with a circulant size
-// that is a multiple of 64, and every fixed degree) that is exactly the edge count.
-// Each check reads and writes only its own entries, so the placement does not change
-// any result.  For quasi-cyclic codes the stable sort keeps each block row's checks
-// consecutive and 64-aligned, so the 64 variables a wavefront updates (consecutive
-// columns of one circulant) also reach 64 distinct banks.
-struct StreamGroupLayout {
-  std::vector<int32_t> slot;  // [64 x groups]: start float | degree << 16 (0 = no check)
-  std::vector<int32_t> pos;   // [nnz]: float index of each edge (CSR order)
-  int64_t floats = 0;
-};
-
-StreamGroupLayout stream_group_layout(const ldpc_graph_s *g) {
-  StreamGroupLayout L;
-  const int m = g->m;
-  std::vector<int32_t> order(m);
-  for (int c = 0; c < m; ++c) order[c] = c;
-  auto deg = [&](int c) { return g->row_ptr[c + 1] - g->row_ptr[c]; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return deg(a) < deg(b); });
-  const int groups = (m + 63) / 64;
-  L.slot.assign((size_t)groups * 64, 0);
-  L.pos.assign((size_t)g->nnz, 0);
-  int64_t start = 0;
-  for (int gi = 0; gi < groups; ++gi) {
-    const int cnt = std::min(64, m - 64 * gi);
-    int dmax = 0;
-    for (int l = 0; l < cnt; ++l) {
-      const int c = order[64 * gi + l], d = deg(c);
-      dmax = std::max(dmax, d);
-      const int64_t base = start + l;
-      L.slot[(size_t)64 * gi + l] = base < 65536 ? (int32_t)(base | ((int64_t)d << 16)) : 0;
-      for (int j = 0; j < d; ++j) L.pos[(size_t)g->row_ptr[c] + j] = (int32_t)std::min<int64_t>(base + 64 * j, INT32_MAX);
-    }
-    start += gi + 1 < groups ? 64 * (int64_t)dmax : 64 * (int64_t)(dmax - 1) + cnt;
-  }
-  L.floats = start;
-  return L;
-}
-
-// Where the check rows sit in LDS.  For a fixed check degree any order of the rows
-// gives the same results (each check reads and writes only its own row), so the rows
-// are placed in the order that keeps the LDS banks of the 64 variables a wavefront
-// updates together as distinct as possible: swaps of two rows' places are kept when
-// they do not raise the summed worst-bank load of the affected (64-variable block,
-// edge rank) groups, ties going by the summed squared loads (a seeded local search,
-// 100 swaps per check).  Returns each
-// variable edge's LDS byte offset in var_edges order.
-std::vector<int32_t> stream_edge_offsets(const ldpc_graph_s *g) {
-  const size_t E = (size_t)g->nnz;
-  std::vector<int32_t> off(E);
-  if (g->m < 2) {
-    for (size_t p = 0; p < E; ++p) off[p] = g->var_edges[p] * 4;
-    return off;
-  }
-  constexpr int kBanks = 64;
-  const int DC = g->dc_max, m = g->m, n = g->n, DV = std::max(1, g->dv_max);
-  // group of edge e: (variable block of 64, rank of e among its variable's edges)
-  std::vector<int32_t> grp(E);
-  for (int v = 0; v < n; ++v)
-    for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p) grp[g->var_edges[p]] = (v >> 6) * DV + (p - g->var_ptr[v]);
-  const size_t ngroups = (size_t)((n + 63) >> 6) * DV;
-  std::vector<uint16_t> cnt(ngroups * kBanks, 0);
-  std::vector<int32_t> slot(m);
-  for (int c = 0; c < m; ++c) slot[c] = c;
-  auto add = [&](int c, int s, int d) {
-    for (int j = 0; j < DC; ++j) cnt[(size_t)grp[(size_t)c * DC + j] * kBanks + (s * DC + j) % kBanks] += d;
-  };
-  for (int c = 0; c < m; ++c) add(c, c, 1);
-  // cost of a group: its worst bank load first, then the sum of squared loads (which
-  // tells apart placements with the same worst load, so the search does not stall on
-  // plateaus: 2.5 -> 2.1 average worst load for (3,6) n=4096 at the same swap count)
-  auto cost = [&](int32_t gid) {
-    const uint16_t *r = &cnt[(size_t)gid * kBanks];
-    int w = 0;
-    long q = 0;
-    for (int b = 0; b < kBanks; ++b) {
-      w = std::max<int>(w, r[b]);
-      q += (long)r[b] * r[b];
-    }
-    return (long)w * 1000000L + q;
-  };
-  std::vector<int32_t> gs;
-  gs.reserve(2 * DC);
-  uint64_t x = 0x9E3779B97F4A7C15ull;  // xorshift64*, fixed seed: the same layout every time
-  auto rnd = [&]() {
-    x ^= x >> 12;
-    x ^= x << 25;
-    x ^= x >> 27;
-    return (x * 0x2545F4914F6CDD1Dull) >> 33;
-  };
-  const long swaps = 100L * m;
-  for (long it = 0; it < swaps; ++it) {
-    const int a = (int)(rnd() % (uint64_t)m), b = (int)(rnd() % (uint64_t)m);
-    if (a == b) continue;
-    gs.clear();
-    for (int j = 0; j < DC; ++j)
-      for (int c : {a, b}) {
-        const int32_t gid = grp[(size_t)c * DC + j];
-        if (std::find(gs.begin(), gs.end(), gid) == gs.end()) gs.push_back(gid);
-      }
-    long before = 0, after = 0;
-    for (int32_t gid : gs) before += cost(gid);
-    add(a, slot[a], -1);
-    add(b, slot[b], -1);
-    add(a, slot[b], 1);
-    add(b, slot[a], 1);
-    for (int32_t gid : gs) after += cost(gid);
-    if (after <= before) {
-      std::swap(slot[a], slot[b]);
-    } else {
-      add(a, slot[b], -1);
-      add(b, slot[a], -1);
-      add(a, slot[a], 1);
-      add(b, slot[b], 1);
-    }
-  }
-  for (size_t p = 0; p < E; ++p) {
-    const int32_t e = g->var_edges[p];
-    off[p] = (slot[e / DC] * DC + e % DC) * 4;
-  }
-  return off;
-}
-
 // Device facts the launch needs (the LDS opt-in of the kernel, compute units, resident
 // workgroups per size) and the LDS placement of the rows, prepared once per graph.
 ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, size_t lds) {
@@ -463,20 +335,6 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
   return LDPC_OK;
 }
 }  // namespace
-
-int64_t stream_x_floats(const ldpc_graph_s *g) {
-  if (kernel_kind(g) < KIND_G8) return g->nnz;  // fixed degrees: one row per check
-  // the group spans of stream_group_layout, from the sorted degrees alone
-  std::vector<int32_t> deg(g->m);
-  for (int c = 0; c < g->m; ++c) deg[c] = g->row_ptr[c + 1] - g->row_ptr[c];
-  std::sort(deg.begin(), deg.end());
-  int64_t floats = 0;
-  for (int i0 = 0; i0 < g->m; i0 += 64) {
-    const int cnt = std::min(64, g->m - i0), dmax = deg[i0 + cnt - 1];
-    floats += i0 + 64 < g->m ? 64 * (int64_t)dmax : 64 * (int64_t)(dmax - 1) + cnt;
-  }
-  return floats;
-}
 
 extern "C" ldpc_status ldpc_stream_lds_bytes(ldpc_graph_t g, size_t *bytes, int32_t *supported) {
   if (!g) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
