@@ -122,25 +122,6 @@ ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32
                            float *posterior, int32_t *iters_used, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
 
-/*
- * ldpc_decode without any allocation, for callers that cannot allocate device memory
- * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
- * tile state lives in a fixed device array of LDPC_NOALLOC_SCRATCH_BYTES that the
- * library holds on each GPU it runs on until the process ends.  Same arguments (minus
- * the workspace), outputs (bit for bit), and errors as ldpc_decode, plus
- * LDPC_ERR_INVALID_ARG when the batch's tile state (ldpc_decode_workspace_size) exceeds
- * the array: at most floor(LDPC_NOALLOC_SCRATCH_BYTES / tile bytes) x 64 words per call
- * (about 384 words of a (3,6) n=4096 code, 17 000 of an n=96 code).  The first call on
- * a device looks up that device's copy of the array (hipGetSymbolAddress); no call
- * allocates or frees memory.  Every call on a GPU uses the same array: calls that
- * overlap on one GPU (different streams, or different threads) race and must be
- * serialised by the caller.  The array needs no clearing between calls.
- */
-#define LDPC_NOALLOC_SCRATCH_BYTES (64u << 20)
-ldpc_status ldpc_decode_noalloc(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
-                                int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
-                                int32_t *iters_used, hipStream_t stream);
-
 /* Decode with an explicit launch shape: waves per workgroup (1..16; ldpc_decode uses 16).
  * Same contract as ldpc_decode. */
 ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
@@ -220,12 +201,21 @@ typedef struct {
  * bit); LDPC_SPLIT_AUTO = every such code whose words fill fewer 64-word tiles than
  * half the GPU's compute units; 0 = none. */
 #define LDPC_SPLIT_AUTO 0xFFFFFFFFu
+/* lanes: words one slot holds at a time (1..64; 0 = automatic: 64, or fewer when the persistent
+ * codes' words would fill fewer 64-word slots than the GPU holds resident, so that the words
+ * spread over more compute units; a code then has at most ceil(batch / lanes) slots).
+ * stream_threads[q]: workgroup size of code q in the stream form (0 = automatic, else as
+ * ldpc_decode_stream's threads); split_slices[q]: workgroups per tile of code q in the split
+ * form (0 = automatic, else as ldpc_decode_split's slices). */
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];
   int32_t refill;
   uint32_t stream_codes;
   uint32_t split_codes;
+  int32_t lanes;
+  int32_t stream_threads[LDPC_MAX_CODES];
+  int32_t split_slices[LDPC_MAX_CODES];
 } ldpc_multi_shape;
 
 /* Shape ldpc_decode_multi would use (automatic slot counts, the stream and split masks
@@ -259,14 +249,21 @@ ldpc_status ldpc_plan_launch(ldpc_plan_t plan, hipStream_t stream);
 ldpc_status ldpc_plan_destroy(ldpc_plan_t plan);
 
 /*
- * Autotuner: times candidate shapes (waves per workgroup x slot scale) of this
- * batched decode on the given inputs and returns the fastest in *best (and its
- * time in *best_ms).  Runs the decode several times, writing the jobs' outputs;
- * allocates and frees its own temporary workspace.  Synchronises `stream`.
+ * Autotuner: times candidate shapes of this batched decode on the given inputs and
+ * returns the fastest in *best (and its time in *best_ms).  Starting from the automatic
+ * choice (stream form for the codes whose word state fits LDS, split form for the other
+ * codes with few tiles, the persistent launch for the rest), it tries every other form
+ * for one code at a time and keeps what is faster (one pass over the codes), then each
+ * stream-form code's workgroup size and each split-form code's slices, then the
+ * persistent launch's shape (waves per workgroup x slot scale x refill threshold x slot
+ * width) when a code uses it.  Every candidate runs three times (the first a warm-up).
+ * Writes the jobs' outputs; allocates and frees its own temporary workspace (the largest
+ * any candidate needs).  Synchronises `stream`.
  */
+#define LDPC_TUNE_PERSISTENT_ONLY 0x1u /* flags: every code in the persistent launch; tune its shape only */
 ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
-                                const int32_t *const *orders, int32_t early_stop, hipStream_t stream,
-                                ldpc_multi_shape *best, float *best_ms);
+                                const int32_t *const *orders, int32_t early_stop, uint32_t flags,
+                                hipStream_t stream, ldpc_multi_shape *best, float *best_ms);
 
 /* ---- differentiable form --------------------------------------------------- */
 

@@ -33,7 +33,7 @@ SIGNATURES = {
                                ctypes.c_int),
     "ldpc_plan_launch": ([_p, _p], ctypes.c_int),
     "ldpc_plan_destroy": ([_p], ctypes.c_int),
-    "ldpc_autotune_multi": ([_p, _i32, _p, _p, _i32, _p, _p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "ldpc_autotune_multi": ([_p, _i32, _p, _p, _i32, _u32, _p, _p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ldpc_unrolled_sizes": ([_p, _i32, _i32, _psz, _psz, _psz], ctypes.c_int),
     "ldpc_unrolled_forward": ([_p, _p, _p, _i32, _i32, _p, _p, ctypes.c_size_t, _p, ctypes.c_size_t, _p],
                               ctypes.c_int),

@@ -38,9 +38,12 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
                                                   const float *__restrict__ init_cv, float *__restrict__ final_cv) {
   __shared__ float stage[TW][TW + 1];
   __shared__ unsigned long long unsat_w[16];
+  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
+  __shared__ float psl_buf[kPsl > 0 ? 16 * kPsl : 1];
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x >> 6;
+  float *psl = kPsl > 0 ? psl_buf + wave * kPsl : nullptr;
   const int tile = blockIdx.x;
   const int cw0 = tile * TW;
   const int nvalid = min(TW, B - cw0);
@@ -62,10 +65,12 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
   for (int it = 0;; ++it) {
     float *En = ((it + 1) & 1) ? st.E1 : st.E0;  // receives E^(it+1)
     int unsat = 0;
-    for (int c = wave; c < g.m; c += W) {
-      int e0, dc;
-      check_range<DC>(g, c, e0, dc);
-      unsat |= check_update<DC>(st.M, En, e0, dc, lane, active);
+    if (active) {  // stopped lanes load nothing
+      for (int c = wave; c < g.m; c += W) {
+        int e0, dc;
+        check_range<DC>(g, c, e0, dc);
+        unsat |= check_update<DC>(st.M, En, e0, dc, lane, true, psl);
+      }
     }
     const unsigned long long b = __ballot(unsat);
     if (lane == 0) unsat_w[wave] = b;
@@ -78,10 +83,12 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
       my_iters = it;
     }
     if (__ballot(active) == 0ull) break;  // same value in every wave of the workgroup
-    for (int v = wave; v < g.n; v += W) {
-      int p0, dv;
-      var_range<DV>(g, v, p0, dv);
-      var_update<DV>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, active);
+    if (active) {
+      for (int v = wave; v < g.n; v += W) {
+        int p0, dv;
+        var_range<DV>(g, v, p0, dv);
+        var_update<DV>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, true);
+      }
     }
     __syncthreads();
   }

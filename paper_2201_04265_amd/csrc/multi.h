@@ -22,6 +22,7 @@ struct MultiArgs {
   MultiJob jobs[LDPC_MAX_CODES];
   int32_t njobs;
   int32_t refill_min;  // pending lanes that trigger a refill
+  int32_t lanes;       // lanes of a slot that take words (the others stay idle)
 };
 
 using MultiKernel = void (*)(MultiArgs, int *, int);
@@ -39,6 +40,7 @@ struct StreamCodes {
   int code[LDPC_MAX_CODES];
   ldpc_graph_s *g[LDPC_MAX_CODES];
   ldpc_job job[LDPC_MAX_CODES];
+  int32_t threads[LDPC_MAX_CODES];  // workgroup size (0 = automatic)
 };
 
 // Codes of a batched decode that run in the split form (host side), each with its
@@ -48,6 +50,7 @@ struct SplitCodes {
   ldpc_graph_s *g[LDPC_MAX_CODES];
   ldpc_job job[LDPC_MAX_CODES];
   void *ws[LDPC_MAX_CODES];
+  int32_t slices[LDPC_MAX_CODES];  // workgroups per tile (0 = automatic)
 };
 
 // A second stream (default priority) and two events: the split-form decodes of a

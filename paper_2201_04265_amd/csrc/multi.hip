@@ -15,6 +15,8 @@
 // Step G of a slot: check phase writes E into E[(G+1)&1] and tests the
 // syndrome of the decisions the messages carry; lanes that stop at G have their last messages in
 // E[G&1] (all lanes of a slot share the step parity, so buffer choice is uniform).
+#include <cmath>
+
 #include "internal.h"
 #include "multi.h"
 #include "tile.h"
@@ -67,10 +69,11 @@ __device__ __forceinline__ int next_word(const MultiJob &J, int w) {
 template <int DV>
 __device__ __forceinline__ void slot_var_phase(const GraphDev &g, TileState st, const float *En, bool running,
                                                bool fresh, int wave, int W, int lane) {
+  if (!(running || fresh)) return;  // idle lanes load nothing
   for (int v = wave; v < g.n; v += W) {
     int p0, dv;
     var_range<DV>(g, v, p0, dv);
-    var_update<DV, true>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, running || fresh, fresh);
+    var_update<DV, true>(st.R, En, st.M, g.var_edges, p0, dv, v, lane, true, fresh);
   }
 }
 
@@ -78,16 +81,16 @@ __device__ __forceinline__ void slot_var_phase(const GraphDev &g, TileState st, 
 // word stops becomes pending; pending lanes are written out and refilled together
 // once at least `refill_min` of them wait or no lane is running.
 template <int DC, int DV>
-__device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop, int refill_min,
-                         unsigned long long *unsat_w, int *lane_word, int wave, int W, int lane) {
+__device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int early_stop, int refill_min, int lanes,
+                         unsigned long long *unsat_w, int *lane_word, int wave, int W, int lane, float *psl) {
   const GraphDev &g = J.g;
   const TileState st = tile_state_block(J.ws + (size_t)local_slot * tile_bytes(g.nnz, g.n), g.nnz, g.n);
 
-  if (wave == 0) {
+  if (wave == 0) {  // lanes >= `lanes` never take a word
     int base = 0;
-    if (lane == 0) base = atomicAdd(counter, TW);
+    if (lane == 0) base = atomicAdd(counter, lanes);
     base = __shfl(base, 0);
-    lane_word[lane] = next_word(J, base + lane);
+    lane_word[lane] = lane < lanes ? next_word(J, base + lane) : -1;
   }
   __syncthreads();
   int word = lane_word[lane];
@@ -104,10 +107,12 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int *counter, int ea
     float *En = ((G + 1) & 1) ? st.E1 : st.E0;
     const bool active = has && !pending;
     int unsat = 0;
-    for (int c = wave; c < g.m; c += W) {
-      int e0, dc;
-      check_range<DC>(g, c, e0, dc);
-      unsat |= check_update<DC>(st.M, En, e0, dc, lane, active);
+    if (active) {  // idle and stopped lanes load nothing
+      for (int c = wave; c < g.m; c += W) {
+        int e0, dc;
+        check_range<DC>(g, c, e0, dc);
+        unsat |= check_update<DC>(st.M, En, e0, dc, lane, true, psl);
+      }
     }
     const unsigned long long b = __ballot(unsat);
     if (lane == 0) unsat_w[wave] = b;
@@ -161,10 +166,13 @@ template <int DC, int DV>
 __global__ void __launch_bounds__(1024) multi_kernel_single(MultiArgs a, int *counters, int early_stop) {
   __shared__ unsigned long long unsat_w[16];
   __shared__ int lane_word[TW];
+  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
+  __shared__ float psl_buf[kPsl > 0 ? 16 * kPsl : 1];
   const int slot = blockIdx.x;
   const int q = find_job(a, slot);
-  run_slot<DC, DV>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, a.refill_min, unsat_w, lane_word,
-                   wave_id(), blockDim.x >> 6, lane_id());
+  run_slot<DC, DV>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, a.refill_min, a.lanes, unsat_w,
+                   lane_word,
+                   wave_id(), blockDim.x >> 6, lane_id(), kPsl > 0 ? psl_buf + wave_id() * kPsl : nullptr);
 }
 
 // Codes of different degree profiles in one launch: the generic (runtime degree)
@@ -173,10 +181,13 @@ template <int DC>
 __global__ void __launch_bounds__(1024) multi_kernel_mixed(MultiArgs a, int *counters, int early_stop) {
   __shared__ unsigned long long unsat_w[16];
   __shared__ int lane_word[TW];
+  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
+  __shared__ float psl_buf[kPsl > 0 ? 16 * kPsl : 1];
   const int slot = blockIdx.x;
   const int q = find_job(a, slot);
   run_slot<DC, -LDPC_MAX_VAR_DEGREE>(a.jobs[q], slot - a.jobs[q].slot0, counters + q, early_stop, a.refill_min,
-                                     unsat_w, lane_word, wave_id(), blockDim.x >> 6, lane_id());
+                                     a.lanes, unsat_w, lane_word, wave_id(), blockDim.x >> 6, lane_id(),
+                                     kPsl > 0 ? psl_buf + wave_id() * kPsl : nullptr);
 }
 
 __global__ void reset_counters(int *counters, int n) {
@@ -228,11 +239,17 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
   if (shape_in) sh = *shape_in;
   for (int q = 0; q < ncodes; ++q)
     if (!graphs[q]) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
+  for (int q = 0; q < ncodes; ++q) {
+    const int nt = sh.stream_threads[q];
+    if (nt != 0 && (nt < 64 || nt > 1024 || nt % 64))
+      return set_error(LDPC_ERR_INVALID_ARG, "stream_threads must be 0 or a multiple of 64 in 64..1024");
+    if (sh.split_slices[q] < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative split_slices");
+  }
   // codes decoded by the stream form: requested ones must fit, AUTO takes those that do
   uint32_t mask = 0;
   for (int q = 0; q < ncodes; ++q) {
     if (!((sh.stream_codes >> q) & 1u)) continue;
-    const ldpc_status st = stream_ready_for(graphs[q], 0);
+    const ldpc_status st = stream_ready_for(graphs[q], sh.stream_threads[q]);
     if (st == LDPC_OK)
       mask |= 1u << q;
     else if (sh.stream_codes != LDPC_STREAM_AUTO || st != LDPC_ERR_UNSUPPORTED)
@@ -268,12 +285,13 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
   if (sh.waves < 1 || sh.waves > 16) return set_error(LDPC_ERR_INVALID_ARG, "waves must be in 1..16");
   if (sh.refill == 0) sh.refill = 1;
   if (sh.refill < 1 || sh.refill > kTile) return set_error(LDPC_ERR_INVALID_ARG, "refill must be in 1..64");
+  if (sh.lanes < 0 || sh.lanes > kTile) return set_error(LDPC_ERR_INVALID_ARG, "lanes must be in 0..64");
   for (int q = 0; q < ncodes; ++q) {
     if (jobs[q].batch < 0 || jobs[q].max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative batch/max_iters");
     if (sh.slots[q] < 0) return set_error(LDPC_ERR_INVALID_ARG, "negative slot count");
   }
   // automatic slot counts: fill the resident capacity, shared in proportion to words x edges
-  bool need_auto = false;
+  bool need_auto = sh.lanes == 0;
   for (int q = 0; q < ncodes; ++q) need_auto |= sh.slots[q] == 0 && jobs[q].batch > 0 && !((mask >> q) & 1u);
   if (need_auto) {
     int dev = 0, cus = 0;
@@ -291,13 +309,23 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
                                                                 64 * sh.waves, 0));
     const double cap = (double)cus * (per_cu > 0 ? per_cu : 1);
     double total = 0;
+    long words = 0;
     for (int q = 0; q < ncodes; ++q)
-      if (!((mask >> q) & 1u)) total += (double)jobs[q].batch * (double)graphs[q]->nnz;
+      if (!((mask >> q) & 1u)) {
+        total += (double)jobs[q].batch * (double)graphs[q]->nnz;
+        words += jobs[q].batch;
+      }
+    if (sh.lanes == 0) {
+      // fewer words than 64 per resident slot: narrower slots spread them over more
+      // compute units (a slot's iteration costs about the same with fewer busy lanes)
+      const long per = (long)std::ceil((double)words / cap);
+      sh.lanes = per >= TW ? TW : std::max(8, (int)((per + 7) / 8 * 8));
+    }
     for (int q = 0; q < ncodes; ++q) {
       if (sh.slots[q] != 0 || jobs[q].batch == 0 || ((mask >> q) & 1u)) continue;
-      const int tiles = (jobs[q].batch + TW - 1) / TW;
-      int s = (int)(cap * (double)jobs[q].batch * (double)graphs[q]->nnz / total + 0.5);
-      sh.slots[q] = std::max(1, std::min(s, tiles));
+      const int peers = (jobs[q].batch + sh.lanes - 1) / sh.lanes;
+      int s = total > 0 ? (int)(cap * (double)jobs[q].batch * (double)graphs[q]->nnz / total + 0.5) : 1;
+      sh.slots[q] = std::max(1, std::min(s, peers));
     }
   }
   size_t bytes = 512;  // counters of the persistent launch, then of the stream-form codes
@@ -318,7 +346,8 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
   *counters = (int *)p;
   p += 512;
   a->njobs = ncodes;
-  a->refill_min = sh.refill;
+  a->refill_min = std::min(sh.refill, sh.lanes > 0 ? sh.lanes : kTile);
+  a->lanes = sh.lanes > 0 ? sh.lanes : kTile;
   int slot = 0;
   for (int q = 0; q < ncodes; ++q) {
     MultiJob &J = a->jobs[q];
@@ -384,7 +413,7 @@ ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves
     for (int i = 0; i < sp->n; ++i) {
       const ldpc_job &j = sp->job[i];
       ldpc_status st = launch_split_decode(sp->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
-                                           j.posterior, j.iters_used, sp->ws[i], 0, split_stream);
+                                           j.posterior, j.iters_used, sp->ws[i], sp->slices[i], split_stream);
       if (st != LDPC_OK) return st;
     }
   }
@@ -393,7 +422,8 @@ ldpc_status multi_enqueue(const MultiArgs &a, int *counters, int grid, int waves
     for (int i = 0; i < sc->n; ++i) {
       const ldpc_job &j = sc->job[i];
       ldpc_status st = launch_stream_decode(sc->g[i], j.llr, false, j.batch, j.max_iters, early_stop, j.hard_bits,
-                                            j.posterior, j.iters_used, counters + 64 + sc->code[i], 0, stream);
+                                            j.posterior, j.iters_used, counters + 64 + sc->code[i], sc->threads[i],
+                                            stream);
       if (st != LDPC_OK) return st;
     }
   }

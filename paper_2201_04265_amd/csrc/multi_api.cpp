@@ -33,6 +33,7 @@ static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, con
     sc->code[sc->n] = q;
     sc->g[sc->n] = graphs[q];
     sc->job[sc->n] = j;
+    sc->threads[sc->n] = sh.stream_threads[q];
     ++sc->n;
   }
   // split-form regions follow the slot states (the layout of multi_resolve's size)
@@ -47,6 +48,7 @@ static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, con
     sp->g[sp->n] = graphs[q];
     sp->job[sp->n] = j;
     sp->ws[sp->n] = (char *)ws + off;
+    sp->slices[sp->n] = sh.split_slices[q];
     ++sp->n;
     off += align256(split_workspace_bytes(graphs[q], j.batch));
   }
@@ -131,68 +133,153 @@ extern "C" ldpc_status ldpc_plan_destroy(ldpc_plan_t plan) {
   return LDPC_OK;
 }
 
-// Candidate shapes: waves per workgroup x a scale of the automatic slot counts x refill threshold.
-extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
-                                           const int32_t *const *orders, int32_t early_stop, hipStream_t stream,
-                                           ldpc_multi_shape *best, float *best_ms) {
-  if (!best) return set_error(LDPC_ERR_INVALID_ARG, "best is NULL");
-  std::vector<ldpc_multi_shape> cands;
-  for (int waves : {8, 16}) {
-    ldpc_multi_shape base{};
-    base.waves = waves;
-    ldpc_multi_shape autos{};
-    ldpc_status st = multi_resolve(graphs, ncodes, jobs, &base, &autos, nullptr);
+namespace {
+
+// Times one shape: a warm-up run and two timed runs of the whole batched call.
+struct Timer {
+  const ldpc_graph_t *graphs;
+  int32_t ncodes;
+  const ldpc_job *jobs;
+  const int32_t *const *orders;
+  int32_t early_stop;
+  hipStream_t stream;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+
+  ldpc_status time(const ldpc_multi_shape &c, float *ms_out) {
+    size_t need = 0;
+    ldpc_status st = multi_resolve(graphs, ncodes, jobs, &c, nullptr, &need);
     if (st != LDPC_OK) return st;
-    for (double scale : {0.5, 1.0, 2.0}) {
-      for (int refill : {1, 4}) {
-        ldpc_multi_shape c = autos;
-        c.refill = refill;
-        for (int q = 0; q < ncodes; ++q) {
-          const int tiles = (jobs[q].batch + kTile - 1) / kTile;
-          c.slots[q] = jobs[q].batch ? std::max(1, std::min(tiles, (int)(autos.slots[q] * scale + 0.5))) : 0;
-        }
-        bool dup = false;
-        for (auto &o : cands)
-          dup |= std::equal(o.slots, o.slots + ncodes, c.slots) && o.waves == c.waves && o.refill == c.refill;
-        if (!dup) cands.push_back(c);
+    if (need > ws_bytes) {  // grow the temporary workspace
+      if (ws) (void)hipFree(ws);
+      ws = nullptr;
+      ws_bytes = 0;
+      if (hipMalloc(&ws, need) != hipSuccess) return set_error(LDPC_ERR_OUT_OF_MEMORY, "autotune workspace");
+      ws_bytes = need;
+    }
+    float tsum = 0;
+    for (int rep = 0; rep < 3; ++rep) {
+      LDPC_HIP_CHECK(hipEventRecord(t0, stream));
+      st = ldpc_decode_multi(graphs, ncodes, jobs, orders, early_stop, &c, ws, ws_bytes, stream);
+      if (st != LDPC_OK) return st;
+      LDPC_HIP_CHECK(hipEventRecord(t1, stream));
+      LDPC_HIP_CHECK(hipEventSynchronize(t1));
+      float ms = 0;
+      LDPC_HIP_CHECK(hipEventElapsedTime(&ms, t0, t1));
+      if (rep > 0) tsum += ms;  // the first run warms up
+    }
+    *ms_out = tsum / 2;
+    return LDPC_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,
+                                           const int32_t *const *orders, int32_t early_stop, uint32_t flags,
+                                           hipStream_t stream, ldpc_multi_shape *best, float *best_ms) {
+  if (!best) return set_error(LDPC_ERR_INVALID_ARG, "best is NULL");
+  if (flags & ~LDPC_TUNE_PERSISTENT_ONLY) return set_error(LDPC_ERR_INVALID_ARG, "unknown flag");
+  const bool forms = !(flags & LDPC_TUNE_PERSISTENT_ONLY);
+  ldpc_multi_shape base{};
+  base.stream_codes = forms ? LDPC_STREAM_AUTO : 0u;
+  base.split_codes = forms ? LDPC_SPLIT_AUTO : 0u;
+  ldpc_multi_shape cur{};
+  ldpc_status st = multi_resolve(graphs, ncodes, jobs, &base, &cur, nullptr);
+  if (st != LDPC_OK) return st;
+  // which codes may take the stream form at all
+  uint32_t can_stream = 0;
+  for (int q = 0; q < ncodes; ++q)
+    if (jobs[q].batch > 0 && stream_ready_for(graphs[q], 0) == LDPC_OK) can_stream |= 1u << q;
+  Timer T{graphs, ncodes, jobs, orders, early_stop, stream};
+  LDPC_HIP_CHECK(hipEventCreate(&T.t0));
+  LDPC_HIP_CHECK(hipEventCreate(&T.t1));
+  float cur_ms = 0;
+  // a candidate is given with explicit forms and automatic persistent slots
+  auto with_forms = [&](uint32_t smask, uint32_t pmask) {
+    ldpc_multi_shape c = cur;
+    c.stream_codes = smask;
+    c.split_codes = pmask;
+    for (int q = 0; q < ncodes; ++q) c.slots[q] = 0;
+    c.lanes = 0;
+    c.waves = 0;
+    return c;
+  };
+  auto attempt = [&](const ldpc_multi_shape &c) -> ldpc_status {
+    float ms = 0;
+    ldpc_status s2 = T.time(c, &ms);
+    if (s2 != LDPC_OK) return s2;
+    if (ms < cur_ms) {
+      cur_ms = ms;
+      cur = c;
+    }
+    return LDPC_OK;
+  };
+  st = T.time(cur, &cur_ms);
+  // 1. the form of each code, one code at a time
+  for (int q = 0; q < ncodes && st == LDPC_OK && forms; ++q) {
+    if (jobs[q].batch == 0) continue;
+    const uint32_t bit = 1u << q;
+    const uint32_t sm = cur.stream_codes & ~bit, pm = cur.split_codes & ~bit;
+    if ((can_stream & bit) && !(cur.stream_codes & bit)) st = attempt(with_forms(sm | bit, pm));
+    if (st == LDPC_OK && !(cur.split_codes & bit) && !(cur.stream_codes & bit)) st = attempt(with_forms(sm, pm | bit));
+    if (st == LDPC_OK && ((cur.stream_codes | cur.split_codes) & bit)) st = attempt(with_forms(sm, pm));
+  }
+  // 2. workgroup sizes of the stream-form codes, slices of the split-form codes
+  for (int q = 0; q < ncodes && st == LDPC_OK; ++q) {
+    if (jobs[q].batch == 0) continue;
+    if ((cur.stream_codes >> q) & 1u) {
+      for (int nt : {256, 512, 1024}) {
+        ldpc_multi_shape c = cur;
+        c.stream_threads[q] = nt;
+        if (stream_ready_for(graphs[q], nt) != LDPC_OK) continue;
+        if ((st = attempt(c)) != LDPC_OK) break;
+      }
+    } else if ((cur.split_codes >> q) & 1u) {
+      for (int sl : {4, 16, 64}) {
+        ldpc_multi_shape c = cur;
+        c.split_slices[q] = sl;
+        if ((st = attempt(c)) != LDPC_OK) break;
       }
     }
   }
-  size_t need = 0;
-  for (auto &c : cands) {
-    size_t b = 0;
-    ldpc_status st = multi_resolve(graphs, ncodes, jobs, &c, nullptr, &b);
-    if (st != LDPC_OK) return st;
-    need = std::max(need, b);
-  }
-  void *ws = nullptr;
-  hipError_t e = hipMalloc(&ws, need);
-  if (e != hipSuccess) return set_error(LDPC_ERR_OUT_OF_MEMORY, "autotune workspace");
-  hipEvent_t t0, t1;
-  (void)hipEventCreate(&t0);
-  (void)hipEventCreate(&t1);
-  float best_t = 1e30f;
-  ldpc_status st = LDPC_OK;
-  for (auto &c : cands) {
-    float tsum = 0;
-    for (int rep = 0; rep < 3 && st == LDPC_OK; ++rep) {
-      (void)hipEventRecord(t0, stream);
-      st = ldpc_decode_multi(graphs, ncodes, jobs, orders, early_stop, &c, ws, need, stream);
-      (void)hipEventRecord(t1, stream);
-      (void)hipEventSynchronize(t1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      if (rep > 0) tsum += ms;  // first run warms up
+  // 3. the persistent launch's shape, when some code uses it
+  bool persistent = false;
+  for (int q = 0; q < ncodes; ++q) persistent |= cur.slots[q] > 0 || (jobs[q].batch > 0 &&
+                                                  !(((cur.stream_codes | cur.split_codes) >> q) & 1u));
+  if (persistent && st == LDPC_OK) {
+    const ldpc_multi_shape start = cur;
+    for (int waves : {8, 16}) {
+      for (int lanes : {0, 64, 32, 16}) {
+        ldpc_multi_shape b0 = start;
+        b0.waves = waves;
+        b0.lanes = lanes;
+        for (int q = 0; q < ncodes; ++q) b0.slots[q] = 0;
+        ldpc_multi_shape autos{};
+        if ((st = multi_resolve(graphs, ncodes, jobs, &b0, &autos, nullptr)) != LDPC_OK) break;
+        for (double scale : {0.5, 1.0, 2.0}) {
+          for (int refill : {1, 4}) {
+            ldpc_multi_shape c = autos;
+            c.refill = refill;
+            for (int q = 0; q < ncodes; ++q) {
+              const int per = (jobs[q].batch + autos.lanes - 1) / std::max(1, autos.lanes);
+              c.slots[q] = autos.slots[q] ? std::max(1, std::min(per, (int)(autos.slots[q] * scale + 0.5))) : 0;
+            }
+            if ((st = attempt(c)) != LDPC_OK) break;
+          }
+          if (st != LDPC_OK) break;
+        }
+        if (st != LDPC_OK) break;
+      }
+      if (st != LDPC_OK) break;
     }
-    if (st != LDPC_OK) break;
-    if (tsum / 2 < best_t) {
-      best_t = tsum / 2;
-      *best = c;
-    }
   }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  (void)hipFree(ws);
-  if (st == LDPC_OK && best_ms) *best_ms = best_t;
-  return st;
+  (void)hipEventDestroy(T.t0);
+  (void)hipEventDestroy(T.t1);
+  if (T.ws) (void)hipFree(T.ws);
+  if (st != LDPC_OK) return st;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return LDPC_OK;
 }

@@ -68,8 +68,9 @@ __device__ __forceinline__ float v2c_store(float x, bool z) {
 //    yl (exact from an fma, plus the constant's low part), and q = 2^-yh (1 - yl ln 2);
 //    FP32, within the hardware exp2's error (0.8 ulp) of e^-|M|.
 //  * joins: the running pairs accumulate in FP64 (full-rate FMA on this chip), so a
-//    chain of joins adds no FP32 rounding; a prefix pair is kept as FP32 d and s - 1
-//    (s - 1 is small when the messages are large, so s keeps its low digits).
+//    chain of joins adds no FP32 rounding.  Only the ratio of a pair matters, so a prefix
+//    pair is kept as one FP32 value, tau = d / s (the pair scaled to s = 1), and the
+//    pair of the others of edge j is (d_suf + tau s_suf, s_suf + tau d_suf).
 //  * output: the ratio s / d in FP64 (the hardware FP64 reciprocal refined by one
 //    Newton step), then rounded once to FP32 for the hardware log2.
 // Signs.  sign_j is the product of the other messages' signs, taken from the IEEE sign
@@ -95,11 +96,11 @@ __device__ __forceinline__ float msg_q(float x16) {
   return fmaf(qh, -yl * kLn2, qh);
 }
 
-// s / d of a pair (s >= d > 0) in FP64: hardware reciprocal (~5e-8) and one Newton step.
-__device__ __forceinline__ double pair_ratio(double d, double s) {
-  const double r0 = __builtin_amdgcn_rcp(d);
-  const double e = fma(-d, r0, 1.0);
-  const double q0 = s * r0;
+// b / a for a > 0 in FP64: hardware reciprocal (~5e-8) and one Newton step.
+__device__ __forceinline__ double quot64(double b, double a) {
+  const double r0 = __builtin_amdgcn_rcp(a);
+  const double e = fma(-a, r0, 1.0);
+  const double q0 = b * r0;
   return fma(q0, e, q0);
 }
 
@@ -109,15 +110,23 @@ __device__ __forceinline__ float ratio_log(double ratio, float &rf) {
   return fabsf(__builtin_amdgcn_logf(rf)) * kLn2;
 }
 
-template <int DC, bool STORED = false, bool AUX = false, class Emit>
+// Prefix pair (d, s) of messages 0..j-1 scaled to s = 1, j >= 1: a single message is
+// (q_0, 1) itself; later ones d / s, rounded to FP32.
+__device__ __forceinline__ float prefix_tau(int j, float q0, double d, double s) {
+  return j == 1 ? q0 : (float)quot64(d, s);
+}
+
+// TS > 0: the prefix taus go to tsl[j * TS] (a lane's column of LDS) instead of a register
+// array, for high degrees in kernels whose registers are short (same values).
+template <int DC, bool STORED = false, bool AUX = false, int TS = 0, class Emit>
 __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emit emit, float *aq = nullptr,
-                                                    float *ar = nullptr) {
+                                                    float *ar = nullptr, float *tsl = nullptr) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   // qs[j] = q_j, and the sign of M_j: for degrees up to 16 the message's bit pattern is
   // kept (mb); above, the sign bit rides in qs[j] so that the messages need not stay live.
   constexpr bool KEEP_BITS = FIXED && DMAX <= 16;
-  float qs[DMAX], pd[DMAX], ps[DMAX];  // ps holds s - 1 of the prefix pairs
+  float qs[DMAX], tr[TS ? 1 : DMAX];  // tr: the prefix taus
   uint32_t mb[KEEP_BITS ? DMAX : 1];
   uint32_t sx = 0;
 #pragma unroll
@@ -136,17 +145,21 @@ __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emi
   }
   // Joins with the empty set (0, 1) are written out: they are exact, and 0 * x cannot
   // be folded by the compiler.  A generic degree's last suffix step keeps the general
-  // form, which gives the same values.  A factor that is the constant 1 of a fresh
-  // pair in one instantiation and a computed 1.0 in another only ever appears in a
-  // plain product feeding an fma's addend (x * 1 rounds to x either way), never as an
-  // fma multiplicand: folding fma(a, 1, b * c) to a + b * c would let the compiler fuse
-  // b * c differently in the two, and fixed and generic degrees must agree bit for bit.
+  // form, which gives the same values.  A suffix pair's s that is the constant 1 in one
+  // instantiation and a computed 1.0 in another only ever meets the form fma(tau, s, d),
+  // where folding x * 1 leaves one rounding of tau + d either way, so fixed and generic
+  // degrees agree bit for bit.
   double d = 0.0, s = 1.0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dc) {
-      pd[j] = (float)d;
-      ps[j] = (float)(s - 1.0);
+      if (j > 0) {  // j = 0: the empty prefix, never read
+        const float t = prefix_tau(j, fabsf(qs[0]), d, s);
+        if constexpr (TS > 0)
+          tsl[j * TS] = t;
+        else
+          tr[j] = t;
+      }
       const double q = (double)fabsf(qs[j]);
       if (j == 0) {
         d = q;
@@ -168,16 +181,18 @@ __device__ __forceinline__ uint32_t check_core_emit(const float *mv, int dc, Emi
       if (j == 0) {
         od = d;
         os = s;
-      } else if (top) {
-        od = (double)pd[j];
-        os = 1.0 + (double)ps[j];
       } else {
-        const double pdj = (double)pd[j], psj = 1.0 + (double)ps[j];
-        od = fma(psj, d, pdj * s);
-        os = fma(pdj, d, psj * s);
+        const double t = (double)(TS > 0 ? tsl[j * TS] : tr[TS > 0 ? 0 : j]);
+        if (top) {
+          od = t;
+          os = 1.0;
+        } else {
+          od = fma(t, s, d);
+          os = fma(t, d, s);
+        }
       }
       float rf;
-      const float mag = ratio_log(pair_ratio(od, os), rf);
+      const float mag = ratio_log(quot64(os, od), rf);
       if (AUX) {
         aq[j] = fabsf(qs[j]);
         ar[j] = fmaxf(rf, 1.0f);
@@ -207,16 +222,16 @@ __device__ __forceinline__ uint32_t check_core(const float *mv, int dc, float *e
 
 // check_core for a runtime degree (DC < 0) on stored messages, in place on the check's
 // own LDS row: the row holds the inputs, then (while the prefix pairs are formed) the
-// second halves of the prefix pairs (s - 1), then the outputs.  Each row entry is read
-// back before it is overwritten by the same thread.  The arithmetic and its order are
-// those of check_core<DC, true>, so the outputs are the same bit for bit; the row
-// stands in for one of the three register arrays of -DC values.  Entry j of the row
-// is row[j * STRIDE] (64 when the 64 checks of a wavefront interleave their rows).
+// prefix taus, then the outputs.  Each row entry is read back before it is overwritten by
+// the same thread.  The arithmetic and its order are those of check_core<DC, true>, so
+// the outputs are the same bit for bit; the row stands in for the register array of
+// prefix taus.  Entry j of the row is row[j * STRIDE] (64 when the 64 checks of a
+// wavefront interleave their rows).
 template <int DC, int STRIDE = 1>
 __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
   static_assert(DC < 0, "runtime degrees only");
   constexpr int DMAX = -DC;
-  float qs[DMAX], pd[DMAX];
+  float qs[DMAX];
   uint32_t sx = 0;
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
@@ -231,8 +246,7 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (j < dc) {
-      pd[j] = (float)d;
-      row[j * STRIDE] = (float)(s - 1.0);
+      if (j > 0) row[j * STRIDE] = prefix_tau(j, fabsf(qs[0]), d, s);
       const double q = (double)fabsf(qs[j]);
       if (j == 0) {
         d = q;
@@ -242,6 +256,9 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
         s = fma(d, q, s);
         d = dn;
       }
+      // one entry at a time: interleaving the unrolled entries would keep their FP64
+      // temporaries live together and push high degrees out of registers
+      if constexpr (DMAX > 8) __builtin_amdgcn_sched_barrier(0);
     }
   }
   d = 0.0;
@@ -254,21 +271,19 @@ __device__ __forceinline__ uint32_t check_core_row(float *row, int dc) {
         od = d;
         os = s;
       } else {
-        // after one element the second half is exactly 1: written as the literal, as it
-        // is a constant in check_core, so that the compiler forms the same operations
-        const double psj = j == 1 ? 1.0 : 1.0 + (double)row[j * STRIDE];
-        const double pdj = (double)pd[j];
-        od = fma(psj, d, pdj * s);
-        os = fma(pdj, d, psj * s);
+        const double t = (double)row[j * STRIDE];
+        od = fma(t, s, d);
+        os = fma(t, d, s);
       }
       float rf;
-      const float mag = ratio_log(pair_ratio(od, os), rf);
+      const float mag = ratio_log(quot64(os, od), rf);
       const uint32_t sgn = (sx ^ __float_as_uint(qs[j])) & 0x80000000u;
       row[j * STRIDE] = __uint_as_float(sgn | __float_as_uint(mag));
       const double q = (double)fabsf(qs[j]);
       const double dn = fma(s, q, d);
       s = fma(d, q, s);
       d = dn;
+      if constexpr (DMAX > 8) __builtin_amdgcn_sched_barrier(0);
     }
   }
   return sx;
@@ -306,9 +321,9 @@ __device__ __forceinline__ int syndrome_bit(uint32_t sx) { return (int)((sx >> 3
 //   Mt: stored v->c messages [nnz][64] (v2c_store); Et: new c->v messages.
 // Returns the parity of the decisions over the check: the syndrome bit (Eq. 1) of
 // the decisions the incoming messages were sent with.
-template <int DC>
-__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et, int e0, int dc,
-                                            int lane, bool store) {
+template <int DC, int TS = 0>
+__device__ __forceinline__ int check_update_core(const float *__restrict__ Mt, float *__restrict__ Et, int e0, int dc,
+                                                 int lane, bool store, float *psl) {
   constexpr int DMAX = DC > 0 ? DC : -DC;
   constexpr bool FIXED = DC > 0;
   float mv[DMAX];
@@ -316,10 +331,33 @@ __device__ __forceinline__ int check_update(const float *__restrict__ Mt, float 
   for (int j = 0; j < DMAX; ++j)
     if (FIXED || j < dc) mv[j] = Mt[(e0 + j) * TW + lane];
   // outputs go straight to Et (every input has been read by then): no output array
-  const uint32_t sx = check_core_emit<DC, true>(mv, dc, [&](int j, float v) {
-    if (store) Et[(e0 + j) * TW + lane] = v;
-  });
+  const uint32_t sx = check_core_emit<DC, true, false, TS>(
+      mv, dc, [&](int j, float v) {
+        if (store) Et[(e0 + j) * TW + lane] = v;
+      },
+      nullptr, nullptr, psl);
   return syndrome_bit(sx);
+}
+
+// Degrees above this keep the prefix taus in LDS (check_update's psl).
+constexpr int kPslDegree = 8;
+
+// LDS floats per wavefront that check_update needs for runtime degrees up to -DC.
+template <int DC>
+constexpr int check_psl_floats() {
+  return (DC > kPslDegree || -DC > kPslDegree) ? (DC > 0 ? DC : -DC) * TW : 0;
+}
+
+// Degrees above kPslDegree keep their prefix taus in the wavefront's LDS block psl
+// ([|DC|][64] floats; this lane's column), which leaves the high-degree kernels one register
+// array of the degree (same values, so the same outputs).
+template <int DC>
+__device__ __forceinline__ int check_update(const float *__restrict__ Mt, float *__restrict__ Et, int e0, int dc,
+                                            int lane, bool store, float *psl = nullptr) {
+  if constexpr (check_psl_floats<DC>() > 0)
+    return check_update_core<DC, TW>(Mt, Et, e0, dc, lane, store, psl + lane);
+  else
+    return check_update_core<DC>(Mt, Et, e0, dc, lane, store, nullptr);
 }
 
 // Variable-node sums (Eqs. 6-7) in FP64: the posterior L = R_v + sum_i x_i (ascending

@@ -65,6 +65,8 @@ template <int DC>
 __global__ void __launch_bounds__(64 * kSplitWaves)
     split_check_kernel(GraphDev g, char *ws, SplitCtl *ctl, int it, int slices) {
   const int lane = lane_id(), wave = wave_id(), W = blockDim.x >> 6;
+  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
+  __shared__ float psl_buf[kPsl > 0 ? kSplitWaves * kPsl : 1];
   const int tile = blockIdx.x / slices, s = blockIdx.x - tile * slices;
   SplitCtl &c = ctl[tile];
   const unsigned long long act = c.active[it & 1];
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(64 * kSplitWaves)
   for (int ch = s * W + wave; ch < g.m; ch += slices * W) {
     int e0, dc;
     check_range<DC>(g, ch, e0, dc);
-    unsat |= check_update<DC>(st.M, En, e0, dc, lane, active);
+    unsat |= check_update<DC>(st.M, En, e0, dc, lane, active, kPsl > 0 ? psl_buf + wave * kPsl : nullptr);
   }
   const unsigned long long b = __ballot(unsat);
   if (lane == 0 && b) atomicOr(&c.unsat[it & 1], b);

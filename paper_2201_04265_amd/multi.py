@@ -26,13 +26,20 @@ SPLIT_AUTO = 0xFFFFFFFF  # every other code with fewer 64-word tiles than half t
 
 class Shape(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32),
-                ("stream_codes", ctypes.c_uint32), ("split_codes", ctypes.c_uint32)]
+                ("stream_codes", ctypes.c_uint32), ("split_codes", ctypes.c_uint32), ("lanes", ctypes.c_int32),
+                ("stream_threads", ctypes.c_int32 * MAX_CODES), ("split_slices", ctypes.c_int32 * MAX_CODES)]
 
     @classmethod
-    def make(cls, waves=0, slots=None, refill=0, stream_codes=0, split_codes=0):
+    def make(cls, waves=0, slots=None, refill=0, stream_codes=0, split_codes=0, lanes=0, stream_threads=None,
+             split_slices=None):
         s = cls()
         s.waves = int(waves)
         s.refill = int(refill)
+        s.lanes = int(lanes)
+        for i, v in enumerate(stream_threads or []):
+            s.stream_threads[i] = int(v)
+        for i, v in enumerate(split_slices or []):
+            s.split_slices[i] = int(v)
         s.stream_codes = int(stream_codes) & 0xFFFFFFFF
         s.split_codes = int(split_codes) & 0xFFFFFFFF
         for i, v in enumerate(slots or []):
@@ -40,7 +47,9 @@ class Shape(ctypes.Structure):
         return s
 
     def as_dict(self, ncodes):
-        d = {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill}
+        d = {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill,
+             "lanes": self.lanes, "stream_threads": [self.stream_threads[i] for i in range(ncodes)],
+             "split_slices": [self.split_slices[i] for i in range(ncodes)]}
         if self.stream_codes:
             d["stream_codes"] = [i for i in range(ncodes) if (self.stream_codes >> i) & 1]
         if self.split_codes:
@@ -102,12 +111,14 @@ class Batch:
                                       workspace.numel(), ctypes.c_void_p(stream_handle(stream))))
         return self.outs
 
-    def autotune(self, early_stop=True, stream=None):
+    def autotune(self, early_stop=True, stream=None, persistent_only=False):
+        """ldpc_autotune_multi: the fastest shape (forms per code and launch shapes) and its time."""
         best = Shape()
         ms = ctypes.c_float()
         check("ldpc_autotune_multi",
               lib().ldpc_autotune_multi(self._gh, self.ncodes, self._jobs, self._orders, int(bool(early_stop)),
-                                        ctypes.c_void_p(stream_handle(stream)), ctypes.byref(best), ctypes.byref(ms)))
+                                        1 if persistent_only else 0, ctypes.c_void_p(stream_handle(stream)),
+                                        ctypes.byref(best), ctypes.byref(ms)))
         return best, ms.value
 
 
@@ -156,8 +167,15 @@ def _signature(graphs, batch: Batch, early_stop) -> str:
         h.update(c.tobytes())
         h.update(v.tobytes())
         h.update(f"{g.m},{g.n},{x.shape[0]},{j.max_iters};".encode())
-    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName}".encode())
+    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName};shape-v2".encode())
     return h.hexdigest()
+
+
+def _mask(codes) -> int:
+    m = 0
+    for q in codes:
+        m |= 1 << int(q)
+    return m
 
 
 def cache_path() -> str:
@@ -165,9 +183,11 @@ def cache_path() -> str:
     return os.path.join(base, "autotune.json")
 
 
-def tuned_shape(batch: Batch, early_stop=True, retune=False) -> Shape:
-    """Shape for this batch from the JSON cache, running the autotuner on a miss."""
-    key = _signature(batch.graphs, batch, early_stop)
+def tuned_shape(batch: Batch, early_stop=True, retune=False, persistent_only=False) -> Shape:
+    """Shape for this batch from the JSON cache (per code signature, batch, iteration limits,
+    early stop and GPU architecture), running the autotuner on a miss.  persistent_only keeps
+    every code in the persistent launch and tunes its shape only."""
+    key = _signature(batch.graphs, batch, early_stop) + (":persistent" if persistent_only else ":forms")
     path = cache_path()
     cache = {}
     if os.path.exists(path):
@@ -178,8 +198,10 @@ def tuned_shape(batch: Batch, early_stop=True, retune=False) -> Shape:
             cache = {}
     if key in cache and not retune:
         d = cache[key]
-        return Shape.make(d["waves"], d["slots"], d.get("refill", 0))
-    best, ms = batch.autotune(early_stop)
+        return Shape.make(d["waves"], d["slots"], d.get("refill", 0), _mask(d.get("stream_codes", [])),
+                          _mask(d.get("split_codes", [])), d.get("lanes", 0), d.get("stream_threads"),
+                          d.get("split_slices"))
+    best, ms = batch.autotune(early_stop, persistent_only=persistent_only)
     cache[key] = dict(best.as_dict(batch.ncodes), ms=ms)
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -145,13 +145,19 @@ def test_autotuner_picks_a_valid_shape(P, tmp_path, monkeypatch):
     g = P.Graph.from_code(code)
     x = torch.from_numpy(W.words("c5", 5, 0, 2.0, 0, 4096, fp32=True).llr).cuda()
     batch = P.Batch([g], [x], 50)
-    shape = P.tuned_shape(batch, True)
-    assert 1 <= shape.waves <= 16 and 1 <= shape.slots[0] <= 64
+    shape = P.tuned_shape(batch, True, persistent_only=True)
+    assert 1 <= shape.waves <= 16 and 1 <= shape.slots[0] <= 4096 and 0 <= shape.lanes <= 64
+    assert shape.stream_codes == 0 and shape.split_codes == 0
     assert (tmp_path / "autotune.json").exists()
-    again = P.tuned_shape(batch, True)  # cache hit
-    assert again.waves == shape.waves and again.slots[0] == shape.slots[0]
+    again = P.tuned_shape(batch, True, persistent_only=True)  # cache hit
+    assert again.waves == shape.waves and again.slots[0] == shape.slots[0] and again.lanes == shape.lanes
     ref = _plain(P, [g], [x], 50)
     _same(ref, _np(batch.run(True, shape)))
+    # with the forms tuned too (stream / split / persistent per code): same outputs
+    fshape = P.tuned_shape(batch, True)
+    _same(ref, _np(batch.run(True, fshape)))
+    again = P.tuned_shape(batch, True)
+    assert again.stream_codes == fshape.stream_codes and again.split_codes == fshape.split_codes
 
 
 def test_c4_stream_codes_equal_per_code_plain(P, c4):

@@ -50,8 +50,13 @@ def one_step(P, oracle_lib, code, llr, ts, label):
     gh, gp, gi, gE = gh.cpu().numpy(), gp.cpu().numpy(), gi.cpu().numpy(), gE.cpu().numpy()
     assert np.all(gi == 1) and np.all(oi == 1)
     rp, rE = _rel(gp, op), _rel(gE, oE)
+    # the same step by the FP32-storage oracle: every stored value correctly rounded
+    _, sp, _, _, sE = oracle_lib.decode_ex(code, X, 1, False, init_cv=S.astype(np.float64), store32=True)
+    ip, iE = _rel(sp, op), _rel(sE, oE)
+    k = np.sqrt(np.mean(rE ** 2)) / max(np.sqrt(np.mean(iE ** 2)), 1e-30)
     print(f"P-step {label}: {X.shape[0]} states (t in {list(ts)}), posterior max {rp.max():.2e} "
-          f"median {np.median(rp):.2e}; c->v max {rE.max():.2e} median {np.median(rE):.2e}", flush=True)
+          f"median {np.median(rp):.2e}; c->v max {rE.max():.2e} median {np.median(rE):.2e}; correctly rounded "
+          f"c->v max {iE.max():.2e}, posterior max {ip.max():.2e}; rms ratio of c->v errors {k:.2f}", flush=True)
     assert rp.max() <= REL, (label, rp.max())
     assert rE.max() <= REL, (label, rE.max())
     diff = gh != oh
