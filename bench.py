@@ -45,59 +45,77 @@ if ROOT not in sys.path:
 
 METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batched"
 
-# HBM bytes per launch on the default workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled
-# by a 1 GiB copy (x1.99994 and x1.0; profiles/decode_c2_sweep.md); valid only for the kernel sources
-# they were measured with (sha1 over "sources"), reported as null otherwise.
+# Counter-measured figures of the default workload's launches: HBM bytes from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (x1.99994 and x1.0), and VALU instructions
+# (SQ_INSTS_VALU) per launch, each valid only for the kernel sources it was measured with (sha1
+# over "sources") and, for the batched form, the launch shape it was measured with; reported as
+# null otherwise (profiles/decode_c2_sweep.md gives the commands).
 _CSRC = "paper_2201_04265_amd/csrc/"
-COUNTER_TRAFFIC = {
+COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "a486dca8e51cf41c62c2126486d017e66fdecd77", "bytes_per_launch": 86295877364, "read_bytes": 14619706804,
-               "write_bytes": 71676170560},
+               "sha1": None, "bytes_per_launch": None, "valu_insts_per_launch": None},
+    "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
+              "sha1": None, "bytes_per_launch": None},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "e57370e3e7bb8656578aacad7c5266ca63170171", "bytes_per_launch": 1639412715159, "read_bytes": 959429640055,
-                "write_bytes": 679983075104},
+                "sha1": None, "bytes_per_launch": None, "shape": None},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
-# VALU issue slots per useful edge-iteration of stream_decode_kernel<6,3>, from its compiled
-# code: 178 VALU instructions per pair of degree-6 checks and 67 per three degree-3 variables
-# (the check loop takes two at a time, the variable loop three), loop control included; one
-# wave64 instruction = 64 lane-slots.  The exp2 / log2 / rcp among them add no issue cycles of
-# their own.
-STREAM_VALU_SLOTS_PER_EDGE = 89 / 6.0 + 67 / 9.0
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# Algorithmic ALU work of one edge-iteration of sum-product decoding (check update of Eq. 5 plus
+# variable update of Eqs. 6-7): two exponentials, two logarithms and two reciprocal-class
+# operations plus about 12.5 plain arithmetic operations, 18.5 lane-operations in all.  The
+# stream form keeps its messages in LDS, so this, not HBM, is its roofline.
+ALU_OPS_PER_EDGE = 18.5
+# One lane-operation per SIMD lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
-def counter_traffic(form, B):
+def _sources_sha1(c):
     import hashlib
 
-    c = COUNTER_TRAFFIC.get(form)
-    if c is None or B != 65536:
-        return None
     h = hashlib.sha1()
     for rel in c["sources"]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    return c["bytes_per_launch"] if h.hexdigest() == c["sha1"] else None
+    return h.hexdigest()
+
+
+def counter(form, B, key, shape=None):
+    """A counter-measured figure of `form` on the default workload, or None when the sources (or
+    the batched launch shape) differ from those it was measured with."""
+    c = COUNTERS.get(form)
+    if c is None or B != 65536 or c.get(key) is None or c["sha1"] is None:
+        return None
+    if _sources_sha1(c) != c["sha1"]:
+        return None
+    if form == "batched" and shape != c.get("shape"):
+        return None
+    return c[key]
 
 
 def roofline(head, code, B):
+    ms = head["ms_per_step"]
     if head["form"] == "stream":
-        a = head["achieved_valu_tops"]
-        return {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": a / VALU_PEAK_TOPS,
-                "traffic": counter_traffic("stream", B), "kernel": head["kernel"],
-                "avg_launch_ms": head["ms_per_step"],
-                "unit_of_work": "useful edge-iteration x VALU instructions per edge-iteration (%.2f lane-slots, "
-                                "compiled code)" % STREAM_VALU_SLOTS_PER_EDGE,
-                "traffic_note": "HBM bytes per launch (counters): messages stay in LDS; beyond the 9n bytes of "
-                                "I/O per word, posterior rewrites of each iteration that overflow L2 (21 % "
-                                "of the HBM peak; the kernel is bound by VALU issue and LDS / barrier "
-                                "latency, and keeping them in LDS costs one resident word per CU)",
+        alg_ops = head["useful_word_iterations"] * code.nnz * ALU_OPS_PER_EDGE
+        a = alg_ops / (ms * 1e-3) / 1e12
+        valu = counter("stream", B, "valu_insts_per_launch")
+        return {"bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "T lane-op/s",
+                "frac": a / VALU_PEAK_TOPS, "traffic": counter("stream", B, "bytes_per_launch"),
+                "kernel": head["kernel"], "avg_launch_ms": ms,
+                "unit_of_work": "useful edge-iteration x %.1f algorithmic lane-operations (2 exp, 2 log, 2 "
+                                "reciprocal-class, 12.5 plain)" % ALU_OPS_PER_EDGE,
+                "alg_ops_per_launch": alg_ops,
+                "issue_frac": (valu * 64 / (ms * 1e-3) / (VALU_PEAK_TOPS * 1e12)) if valu else None,
+                "issue_note": "VALU instructions of the launch (SQ_INSTS_VALU counters, 64 lane-slots each) over "
+                              "the VALU lane-slots of the launch time; null when the kernel sources differ from "
+                              "those counted",
+                "traffic_note": "HBM bytes per launch (counters): messages stay in LDS; beyond the 9n bytes of I/O "
+                                "per word, posterior rewrites that overflow L2",
                 "hbm_alg_gb_s_equivalent": head["achieved_gb_s"]}
     return {"bound": "hbm", "achieved": head["achieved_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": head["achieved_gb_s"] / HBM_PEAK_GBS,
-            "traffic": counter_traffic(head["form"], B),
-            "kernel": head["kernel"], "avg_launch_ms": head["ms_per_step"],
+            "traffic": counter(head["form"], B, "bytes_per_launch", head.get("shape")),
+            "kernel": head["kernel"], "avg_launch_ms": ms,
             "alg_bytes_per_launch": head["alg_bytes_per_launch"],
             "bytes_per_word_iteration": bytes_per_word_iteration(code.n, code.nnz),
             "unit_of_work": "useful word-iteration (sum of iterations used over words) plus LLR in / posterior "
@@ -206,7 +224,7 @@ def fixed_run(torch, fn, stream, words, code, form):
     eu = words * MAX_ITERS * code.nnz / (ms * 1e-3)
     d = {"ms": ms, "coded_gbit_s": words * code.n / (ms * 1e-3) / 1e9, "edge_updates_per_s": eu}
     if form == "stream":
-        d["valu_frac"] = eu * STREAM_VALU_SLOTS_PER_EDGE / (VALU_PEAK_TOPS * 1e12)
+        d["alu_frac"] = eu * ALU_OPS_PER_EDGE / (VALU_PEAK_TOPS * 1e12)
     else:
         alg = words * (MAX_ITERS * bytes_per_word_iteration(code.n, code.nnz) + io_bytes_per_word(code.n))
         d["hbm_alg_gb_s"] = alg / (ms * 1e-3) / 1e9
@@ -371,7 +389,7 @@ def bench_c4(args, torch, P):
 
     ms_plain_conc = time_launches(torch, plain_concurrent, args.steps, args.warmup, stream)
     batch = P.Batch(graphs, llrs, MAX_ITERS)
-    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True, persistent_only=True)
     resolved, _ = batch.resolve(shape)
     ws = batch.workspace(shape)
     ms_batched = time_launches(torch, lambda: batch.run(True, shape, ws), args.steps, args.warmup, stream)
@@ -397,6 +415,12 @@ def bench_c4(args, torch, P):
     sws = sbatch.workspace(sshape)
     ms_split = time_launches(torch, lambda: sbatch.run(True, sshape, sws), args.steps, args.warmup, stream)
     splitc = [bool((sresolved.split_codes >> i) & 1) for i in range(len(codes))]
+    # the autotuner's choice of form per code (stream / split / persistent) and launch shapes
+    tbatch = P.Batch(graphs, llrs, MAX_ITERS)
+    tshape = sshape if args.no_autotune else P.tuned_shape(tbatch, True)
+    tresolved, _ = tbatch.resolve(tshape)
+    tws = tbatch.workspace(tshape)
+    ms_tuned = time_launches(torch, lambda: tbatch.run(True, tshape, tws), args.steps, args.warmup, stream)
     bits = sum(int(x.numel()) for x in llrs)
     useful = sum(int(o[2].to(torch.int64).sum().item()) * c.nnz for o, c in zip(batch.outs, codes))
     per_code = []
@@ -406,6 +430,7 @@ def bench_c4(args, torch, P):
         same &= all(bool(torch.equal(a, b)) for a, b in zip(bo, po))
         same &= all(bool(torch.equal(a, b)) for a, b in zip(hbatch.outs[i], po))
         same &= all(bool(torch.equal(a, b)) for a, b in zip(sbatch.outs[i], po))
+        same &= all(bool(torch.equal(a, b)) for a, b in zip(tbatch.outs[i], po))
         per_code.append({"code": c.name, "n": c.n, "edges": c.nnz, "words": counts[i], "ebn0_db": float(ebn0[i]),
                          "mean_iters": float(bo[2].float().mean().item()),
                          "ber_coded": float((bo[0] != cws[i]).float().mean().item()),
@@ -431,6 +456,8 @@ def bench_c4(args, torch, P):
             "batched_with_stream_and_split_codes_ms": avg(ms_split),
             "split_codes": [codes[i].name for i, f in enumerate(splitc) if f],
             "speedup_with_stream_and_split_codes_vs_per_code_plain": avg(ms_plain) / avg(ms_split),
+            "tuned_forms_ms": avg(ms_tuned), "tuned_shape": tresolved.as_dict(len(codes)),
+            "tuned_vs_heuristic": avg(ms_split) / avg(ms_tuned),
             "edge_updates_per_s": useful / (avg(ms_batched) * 1e-3), "shape": resolved.as_dict(len(codes)),
             "outputs_bitwise_equal": same, "per_code": per_code}
 
@@ -459,7 +486,7 @@ def bench_c3(args, torch, P):
                              args.warmup, stream)
     del ws
     batch = P.Batch([g], [llr], T)
-    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, True, persistent_only=True)
     resolved, _ = batch.resolve(shape)
     bws = batch.workspace(shape)
     ms_batched = time_launches(torch, lambda: batch.run(True, shape, bws), args.steps, args.warmup, stream)
@@ -589,10 +616,23 @@ def bench_paper(args, torch, P):
         log(f"[bench] {c.name}: plain {avg(ms_p):.3f} ms, stream {avg(ms_s):.3f} ms, one vector {avg(ms_1):.3f} ms")
 
     batch = P.Batch(graphs, llrs, T)
-    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, False)
+    shape = P.Shape.make() if args.no_autotune else P.tuned_shape(batch, False, persistent_only=True)
     resolved, _ = batch.resolve(shape)
     bws = batch.workspace(shape)
     ms_b = time_launches(torch, lambda: batch.run(False, shape, bws), args.steps, args.warmup, stream)
+    # the three codes in one batched call: the library's automatic forms, and the autotuner's
+    abatch = P.Batch(graphs, llrs, T)
+    ashape = P.Shape.make(stream_codes=P.STREAM_AUTO, split_codes=P.SPLIT_AUTO)
+    aresolved, _ = abatch.resolve(ashape)
+    aws = abatch.workspace(ashape)
+    ms_a = time_launches(torch, lambda: abatch.run(False, ashape, aws), args.steps, args.warmup, stream)
+    tbatch = P.Batch(graphs, llrs, T)
+    tshape = ashape if args.no_autotune else P.tuned_shape(tbatch, False)
+    tresolved, _ = tbatch.resolve(tshape)
+    tws = tbatch.workspace(tshape)
+    ms_t = time_launches(torch, lambda: tbatch.run(False, tshape, tws), args.steps, args.warmup, stream)
+    same_forms = all(bool(torch.equal(a, b)) for i in range(len(codes))
+                     for a, b in zip(abatch.outs[i], tbatch.outs[i]))
 
     sample = max(1, min(args.paper_cpu_sample, nvec))
     top = oracle.default_threads()
@@ -627,6 +667,12 @@ def bench_paper(args, torch, P):
             "batched_three_codes_one_launch": {"ms": avg(ms_b), "us_per_vector": avg(ms_b) * 1e3 / total_vec,
                                                "coded_gbit_s": bits / (avg(ms_b) * 1e-3) / 1e9,
                                                "shape": resolved.as_dict(len(codes))},
+            "batched_three_codes_automatic_forms": {"ms": avg(ms_a), "us_per_vector": avg(ms_a) * 1e3 / total_vec,
+                                                    "shape": aresolved.as_dict(len(codes))},
+            "batched_three_codes_tuned_forms": {"ms": avg(ms_t), "us_per_vector": avg(ms_t) * 1e3 / total_vec,
+                                                "shape": tresolved.as_dict(len(codes)),
+                                                "tuned_vs_automatic": avg(ms_a) / avg(ms_t),
+                                                "outputs_equal_to_automatic": same_forms},
             "stream_coded_gbit_s": bits / (sum(r["stream_us_per_vector"] for r in per_code) * nvec * 1e-6) / 1e9,
             "cpu_baseline": {"value": cpu_us, "unit": "us/vector", "cores": top, "kind": "oracle",
                              "sample": f"first {sample} vectors of each code, FP64 C oracle, 10 iterations, "
@@ -724,7 +770,7 @@ def main():
             shape = P.Shape.make()
         else:
             t0 = time.time()
-            shape = P.tuned_shape(batch, True)
+            shape = P.tuned_shape(batch, True, persistent_only=True)
             log(f"[bench] autotuned shape {shape.as_dict(1)} in {time.time() - t0:.1f}s")
         resolved, _ = batch.resolve(shape)
         ws = batch.workspace(shape)
@@ -749,8 +795,8 @@ def main():
         results["stream"] = summarize(torch, "stream", ms, outs, cw, ebn0s, B, code,
                                       {"kernel": "stream_decode_kernel<6,3>", "threads": 512})
         r = results["stream"]
-        r["valu_slots_per_edge_iteration"] = STREAM_VALU_SLOTS_PER_EDGE
-        r["achieved_valu_tops"] = r["edge_updates_per_s"] * STREAM_VALU_SLOTS_PER_EDGE / 1e12
+        r["alu_ops_per_edge_iteration"] = ALU_OPS_PER_EDGE
+        r["achieved_alu_tops"] = r["edge_updates_per_s"] * ALU_OPS_PER_EDGE / 1e12
         if "plain" in results:
             r["bitwise_equal_to_plain"] = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain_outs))
         log(f"[bench] stream: {r['ms_per_step']:.1f} ms/step")
@@ -772,14 +818,12 @@ def main():
         log(f"[bench] on-device generation {generation['generate_ms']:.2f} ms, whole sweep {generation['sweep_ms']:.1f} ms")
 
     for name, r in results.items():  # counter-measured HBM bytes beside the algorithmic ones
-        t = counter_traffic(name, B)
+        t = counter(name, B, "bytes_per_launch", r.get("shape"))
+        r["counter_bytes_per_launch"] = t
         if t is not None:
-            r["counter_bytes_per_launch"] = t
             r["counter_gb_s"] = t / (r["ms_per_step"] * 1e-3) / 1e9
             r["counter_hbm_frac"] = r["counter_gb_s"] / HBM_PEAK_GBS
-            r["counter_note"] = ("HBM bytes of one launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a "
-                                 "1 GiB copy" + (" (taken with the library's default shape)" if name == "batched"
-                                                 else ""))
+            r["counter_note"] = "HBM bytes of one launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy"
     head = results.get("stream") or results.get("batched") or results["plain"]
     result = {
         "metric": METRIC,

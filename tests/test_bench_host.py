@@ -1,5 +1,5 @@
 """Host-side contract of bench.py (no GPU): the refusal of runs on several GPUs, the byte model of
-the HBM rooflines, and the counter-traffic table keyed to the kernel sources."""
+the HBM rooflines, and the counter table keyed to the kernel sources and launch shape."""
 import json
 import os
 import subprocess
@@ -29,20 +29,31 @@ def test_byte_model_of_the_hbm_forms():
     assert bench.io_bytes_per_word(n) == 9 * n
 
 
-def test_valu_model_and_peaks():
-    assert bench.STREAM_VALU_SLOTS_PER_EDGE == pytest.approx(89 / 6 + 67 / 9)
+def test_alu_model_and_peaks():
+    # 2 exp + 2 log + 2 reciprocal-class + 12.5 plain lane-operations per edge-iteration
+    assert bench.ALU_OPS_PER_EDGE == pytest.approx(2 + 2 + 2 + 12.5)
     assert bench.VALU_PEAK_TOPS == pytest.approx(256 * 64 * 2.4e9 / 1e12)
     assert bench.HBM_PEAK_GBS == 8000.0
 
 
-def test_counter_traffic_only_for_the_measured_sources_and_batch():
-    for form in ("stream", "batched"):
-        c = bench.COUNTER_TRAFFIC[form]
-        assert c["bytes_per_launch"] == c["read_bytes"] + c["write_bytes"]
-        assert bench.counter_traffic(form, 1000) is None  # another batch: not the measured launch
-        got = bench.counter_traffic(form, 65536)
+def test_counters_only_for_the_measured_sources_batch_and_shape(tmp_path, monkeypatch):
+    for form, c in bench.COUNTERS.items():
+        assert bench.counter(form, 1000, "bytes_per_launch") is None  # another batch: not the measured launch
+        got = bench.counter(form, 65536, "bytes_per_launch", c.get("shape"))
         assert got in (None, c["bytes_per_launch"])  # None once the kernel sources change
-    assert bench.counter_traffic("plain", 65536) is None
+        if c.get("sha1") and c.get("bytes_per_launch"):
+            # an edit of any listed source nulls the figure
+            src = os.path.join(ROOT, c["sources"][0])
+            fake = tmp_path / "src"
+            fake.write_bytes(open(src, "rb").read() + b"\n")
+            c2 = dict(c, sources=[str(fake)] + c["sources"][1:])
+            monkeypatch.setitem(bench.COUNTERS, form, c2)
+            assert bench.counter(form, 65536, "bytes_per_launch", c.get("shape")) is None
+            monkeypatch.setitem(bench.COUNTERS, form, c)
+    c = bench.COUNTERS["batched"]
+    if c.get("sha1") and c.get("bytes_per_launch") and c.get("shape"):
+        other = dict(c["shape"], waves=(4 if c["shape"].get("waves") != 4 else 8))
+        assert bench.counter("batched", 65536, "bytes_per_launch", other) is None  # another launch shape
 
 
 def test_cpu_model_is_a_name():
