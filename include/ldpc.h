@@ -122,6 +122,25 @@ ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32
                            float *posterior, int32_t *iters_used, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
 
+/*
+ * ldpc_decode without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * tile state lives in a fixed device array of LDPC_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.  Same arguments (minus
+ * the workspace), outputs (bit for bit), and errors as ldpc_decode, plus
+ * LDPC_ERR_INVALID_ARG when the batch's tile state (ldpc_decode_workspace_size) exceeds
+ * the array: at most floor(LDPC_NOALLOC_SCRATCH_BYTES / tile bytes) x 64 words per call
+ * (about 384 words of a (3,6) n=4096 code, 17 000 of an n=96 code).  The first call on
+ * a device looks up that device's copy of the array (hipGetSymbolAddress); no call
+ * allocates or frees memory.  Every call on a GPU uses the same array: calls that
+ * overlap on one GPU (different streams, or different threads) race and must be
+ * serialised by the caller.  The array needs no clearing between calls.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (64u << 20)
+ldpc_status ldpc_decode_noalloc(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
+                                int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
+                                int32_t *iters_used, hipStream_t stream);
+
 /* Decode with an explicit launch shape: waves per workgroup (1..16; ldpc_decode uses 16).
  * Same contract as ldpc_decode. */
 ldpc_status ldpc_decode_config(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,

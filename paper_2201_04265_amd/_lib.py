@@ -21,6 +21,7 @@ SIGNATURES = {
     "ldpc_decode_workspace_size": ([_p, _i32, _u32, _psz], ctypes.c_int),
     "ldpc_decode": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
     "ldpc_decode_ex": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p], ctypes.c_int),
+    "ldpc_decode_noalloc": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p], ctypes.c_int),
     "ldpc_decode_config": ([_p, _p, _i32, _i32, _i32, _u32, _p, _p, _p, _p, ctypes.c_size_t, _i32, _p],
                            ctypes.c_int),
     "ldpc_stream_lds_bytes": ([_p, _psz, _pi32], ctypes.c_int),

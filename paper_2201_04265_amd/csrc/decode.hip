@@ -25,6 +25,8 @@
 // State in and out: a decode may start from caller c->v messages E^(0) (placed in E0,
 // then one variable phase on them gives L^(0), z^(0) and M^(1)), and may write each
 // word's E of its last iteration back out.
+#include <mutex>
+
 #include "internal.h"
 #include "tile.h"
 
@@ -169,4 +171,59 @@ ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr
                      (int)(early_stop != 0), (char *)ws, hard, post, iters, init_cv, final_cv);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;
+}
+
+// ---- allocation-free entry point ----------------------------------------------------
+//
+// The tile state of ldpc_decode_noalloc lives in a fixed array in device memory that the
+// library's code object holds on every GPU it is loaded on (LDPC_NOALLOC_SCRATCH_BYTES).
+// Host code must not use the array's name as an address: each device's copy is found
+// once with hipGetSymbolAddress (with that device current) and that pointer is what the
+// kernels receive.
+static __device__ __align__(256) unsigned char scratch[LDPC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+ldpc_status scratch_for_current_device(void **out) {
+  int dev = 0;
+  LDPC_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LDPC_ERR_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_error(LDPC_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LDPC_OK;
+}
+}  // namespace
+
+extern "C" ldpc_status ldpc_decode_noalloc(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters,
+                                           int32_t early_stop, uint32_t flags, uint8_t *hard_bits, float *posterior,
+                                           int32_t *iters_used, hipStream_t stream) {
+  if (!g) return set_error(LDPC_ERR_INVALID_ARG, "graph is NULL");
+  if (batch < 0) return set_error(LDPC_ERR_INVALID_ARG, "batch < 0");
+  if (max_iters < 0) return set_error(LDPC_ERR_INVALID_ARG, "max_iters < 0");
+  if (flags & ~LDPC_LLR_F64) return set_error(LDPC_ERR_INVALID_ARG, "unknown flag");
+  if (batch == 0) return LDPC_OK;
+  if (!llr || !hard_bits || !posterior || !iters_used) return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
+  const size_t need = plain_workspace_bytes(g, batch);
+  if (need > (size_t)LDPC_NOALLOC_SCRATCH_BYTES)
+    return set_error(LDPC_ERR_INVALID_ARG,
+                     "batch needs " + std::to_string(need) + " bytes of tile state, above the fixed " +
+                         std::to_string((size_t)LDPC_NOALLOC_SCRATCH_BYTES) + "-byte scratch (at most " +
+                         std::to_string(LDPC_NOALLOC_SCRATCH_BYTES / tile_bytes(g->nnz, g->n) * kTile) +
+                         " words of this code per call)");
+  void *ws = nullptr;
+  ldpc_status st = scratch_for_current_device(&ws);
+  if (st != LDPC_OK) return st;
+  // 16 waves per tile, as ldpc_decode
+  return launch_plain_decode(g, llr, (flags & LDPC_LLR_F64) != 0, batch, max_iters, early_stop, hard_bits, posterior,
+                             iters_used, ws, (size_t)LDPC_NOALLOC_SCRATCH_BYTES, 16, stream);
 }
