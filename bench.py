@@ -46,18 +46,21 @@ if ROOT not in sys.path:
 METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batched"
 
 # Counter-measured figures of the default workload's launches: HBM bytes from rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (x1.99994 and x1.0), and VALU instructions
+# FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (x1.99996 and x1.0), and VALU instructions
 # (SQ_INSTS_VALU) per launch, each valid only for the kernel sources it was measured with (sha1
 # over "sources") and, for the batched form, the launch shape it was measured with; reported as
 # null otherwise (profiles/decode_c2_sweep.md gives the commands).
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": None, "bytes_per_launch": None, "valu_insts_per_launch": None},
+               "sha1": "3180728838fe588bce53458e489db05a2327cbdb", "bytes_per_launch": 70043147444,
+               "valu_insts_per_launch": 43903465560},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": None, "bytes_per_launch": None},
+              "sha1": "9b6a51c4898facfd90ec0fb11645087404a1b474", "bytes_per_launch": 1804775474886},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": None, "bytes_per_launch": None, "shape": None},
+                "sha1": "c8b85da829ed61534d9a6a34bb1635ab1325e217", "bytes_per_launch": 1599788648506,
+                "shape": {"waves": 8, "slots": [768], "refill": 1, "lanes": 64, "stream_threads": [0],
+                          "split_slices": [0]}},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50

@@ -220,12 +220,22 @@ typedef struct {
  * bit); LDPC_SPLIT_AUTO = every such code whose words fill fewer 64-word tiles than
  * half the GPU's compute units; 0 = none. */
 #define LDPC_SPLIT_AUTO 0xFFFFFFFFu
-/* lanes: words one slot holds at a time (1..64; 0 = automatic: 64, or fewer when the persistent
- * codes' words would fill fewer 64-word slots than the GPU holds resident, so that the words
- * spread over more compute units; a code then has at most ceil(batch / lanes) slots).
+/* lanes: words one slot holds at a time (1..64; 0 = 64); a code has at most ceil(batch / lanes)
+ * slots.
  * stream_threads[q]: workgroup size of code q in the stream form (0 = automatic, else as
  * ldpc_decode_stream's threads); split_slices[q]: workgroups per tile of code q in the split
- * form (0 = automatic, else as ldpc_decode_split's slices). */
+ * form (0 = automatic, else as ldpc_decode_split's slices).
+ * span[q]: workgroups that share each slot of code q (1..64; 0 = automatic: 1, or, when the
+ * code's slot count is automatic and its words fill fewer slots than its share of the resident
+ * capacity, that share divided by its slots).  A slot of span > 1 ("group slot") splits every
+ * check and variable phase over its workgroups, which meet at a barrier in global memory after
+ * each phase: a batch with few words of a long code then keeps many compute units busy.  Its
+ * workgroups wait for each other, so a launch with group slots must fit the GPU at once:
+ * sum over codes of slots x span <= resident workgroups of the kernel (automatic spans shrink to
+ * fit; explicit ones that do not fit are LDPC_ERR_INVALID_ARG).  The barrier gives up after
+ * seconds of waiting (possible only if other work keeps the launch's workgroups from becoming
+ * resident that long); the int at byte offset LDPC_MULTI_FAULT_OFFSET of the workspace is then
+ * nonzero after the launch and its outputs are invalid. */
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];
@@ -235,7 +245,9 @@ typedef struct {
   int32_t lanes;
   int32_t stream_threads[LDPC_MAX_CODES];
   int32_t split_slices[LDPC_MAX_CODES];
+  int32_t span[LDPC_MAX_CODES];
 } ldpc_multi_shape;
+#define LDPC_MULTI_FAULT_OFFSET 480
 
 /* Shape ldpc_decode_multi would use (automatic slot counts, the stream and split masks
  * filled in; codes in stream or split form get 0 slots) and its workspace size. */

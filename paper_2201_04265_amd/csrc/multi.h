@@ -2,6 +2,19 @@
 #pragma once
 
 #include "internal.h"
+#include "tile.h"
+
+// Ints per group slot (span > 1) in global memory: the barrier's arrival counter, two
+// 64-bit unsatisfied-check masks (even / odd steps) and the lane -> word table.
+constexpr int kSyncInts = 128;
+constexpr int kSyncMasks = 2;       // offset of the two masks (8-byte aligned)
+constexpr int kSyncLaneWords = 64;  // offset of the lane -> word table
+// Largest number of workgroups per slot.
+constexpr int kMaxSpan = 64;
+// Index (in ints) of the launch's fault word in the counter block at the start of the
+// workspace: nonzero after a launch iff a group slot's barrier wait gave up.
+constexpr int kFaultInt = 120;
+static_assert(kFaultInt * 4 == LDPC_MULTI_FAULT_OFFSET, "fault word offset");
 
 // One code of a batched launch, passed by value in the kernel arguments.
 struct MultiJob {
@@ -13,7 +26,9 @@ struct MultiJob {
   const int32_t *order;  // optional word order (NULL: 0..batch-1)
   char *ws;              // nslots tile states of this code
   int32_t batch, max_iters;
-  int32_t slot0, nslots;  // workgroups [slot0, slot0 + nslots) serve this code
+  int32_t wg0, nslots;    // workgroups [wg0, wg0 + nslots x span) serve this code's slots
+  int32_t span;           // workgroups per slot
+  int32_t *sync;          // span > 1: nslots x kSyncInts ints (zeroed before the launch)
   int32_t kind;           // degree specialisation (KernelKind)
   int32_t dc_max;         // largest check degree
 };
@@ -27,6 +42,12 @@ struct MultiArgs {
 
 using MultiKernel = void (*)(MultiArgs, int *, int);
 MultiKernel multi_kernel_for(const MultiArgs &a);
+
+// Workspace bytes of code q's slots: their tile states, then (group slots) their barrier words.
+inline size_t slot_region_bytes(const ldpc_graph_s *g, const ldpc_multi_shape &sh, int q) {
+  const size_t tiles = (size_t)sh.slots[q] * ldpc::tile_bytes(g->nnz, g->n);
+  return tiles + (sh.span[q] > 1 ? (size_t)sh.slots[q] * kSyncInts * sizeof(int32_t) : 0);
+}
 
 // Validates the jobs, fills automatic slot counts and returns the workspace size.
 ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_job *jobs,

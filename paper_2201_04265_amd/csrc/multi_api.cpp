@@ -38,7 +38,7 @@ static ldpc_status multi_prepare(const ldpc_graph_t *graphs, int32_t ncodes, con
   }
   // split-form regions follow the slot states (the layout of multi_resolve's size)
   size_t off = 512;
-  for (int q = 0; q < ncodes; ++q) off += (size_t)sh.slots[q] * ldpc::tile_bytes(graphs[q]->nnz, graphs[q]->n);
+  for (int q = 0; q < ncodes; ++q) off += slot_region_bytes(graphs[q], sh, q);
   sp->n = 0;
   for (int q = 0; q < ncodes; ++q) {
     if (!((sh.split_codes >> q) & 1u)) continue;
@@ -207,6 +207,8 @@ extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t n
     return c;
   };
   auto attempt = [&](const ldpc_multi_shape &c) -> ldpc_status {
+    // shapes the launch cannot take (group slots beyond the resident capacity) are skipped
+    if (multi_resolve(graphs, ncodes, jobs, &c, nullptr, nullptr) != LDPC_OK) return LDPC_OK;
     float ms = 0;
     ldpc_status s2 = T.time(c, &ms);
     if (s2 != LDPC_OK) return s2;
@@ -251,13 +253,16 @@ extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t n
   if (persistent && st == LDPC_OK) {
     const ldpc_multi_shape start = cur;
     for (int waves : {8, 16}) {
-      for (int lanes : {0, 64, 32, 16}) {
+      for (int lanes : {64, 32, 16}) {
         ldpc_multi_shape b0 = start;
         b0.waves = waves;
         b0.lanes = lanes;
-        for (int q = 0; q < ncodes; ++q) b0.slots[q] = 0;
+        for (int q = 0; q < ncodes; ++q) b0.slots[q] = b0.span[q] = 0;
         ldpc_multi_shape autos{};
         if ((st = multi_resolve(graphs, ncodes, jobs, &b0, &autos, nullptr)) != LDPC_OK) break;
+        bool groups = false;
+        for (int q = 0; q < ncodes; ++q) groups |= autos.span[q] > 1;
+        // slot counts scaled around the automatic ones (automatic spans kept)
         for (double scale : {0.5, 1.0, 2.0}) {
           for (int refill : {1, 4}) {
             ldpc_multi_shape c = autos;
@@ -269,6 +274,14 @@ extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t n
             if ((st = attempt(c)) != LDPC_OK) break;
           }
           if (st != LDPC_OK) break;
+        }
+        // group slots: half and a quarter of the automatic spans, and none
+        for (int div : {2, 4, 0}) {
+          if (!groups || st != LDPC_OK) break;
+          ldpc_multi_shape c = autos;
+          for (int q = 0; q < ncodes; ++q)
+            if (autos.span[q] > 1) c.span[q] = div ? std::max(1, autos.span[q] / div) : 1;
+          st = attempt(c);
         }
         if (st != LDPC_OK) break;
       }

@@ -17,6 +17,16 @@ constexpr float kLmax = 20.0f;  // saturation of variable-to-check messages
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Graph tables (CSR offsets, edge numbering) never change while a decode runs.  Their
+// loads go through the constant address space, so an index the whole wavefront shares is
+// fetched with a scalar load whatever else the kernel stores to global memory (through a
+// plain pointer the compiler must assume those stores may clobber it, and falls back to
+// a vector load per wavefront).
+template <class T>
+__device__ __forceinline__ T ld_graph(const T *p, size_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // Workgroup barrier that orders LDS only: global loads and stores in flight are not
 // waited for.  For kernels whose threads exchange data only through LDS (what they
 // write to global memory is read by later launches or by the writing thread itself).
@@ -390,7 +400,7 @@ __device__ __forceinline__ double var_posterior(float r, const float *__restrict
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (FIXED || j < dv) {
-      eid[j] = var_edges[p0 + j];
+      eid[j] = ld_graph(var_edges, p0 + j);
       ev[j] = Et[eid[j] * TW + lane];
     }
   }

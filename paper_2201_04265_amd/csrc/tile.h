@@ -38,8 +38,8 @@ __device__ __forceinline__ void var_range(const GraphDev &g, int v, int &p0, int
     p0 = v * DV;
     dv = DV;
   } else {
-    p0 = g.var_ptr[v];
-    dv = g.var_ptr[v + 1] - p0;
+    p0 = ld_graph(g.var_ptr, v);
+    dv = ld_graph(g.var_ptr, v + 1) - p0;
   }
 }
 
@@ -49,8 +49,8 @@ __device__ __forceinline__ void check_range(const GraphDev &g, int c, int &e0, i
     e0 = c * DC;
     dc = DC;
   } else {
-    e0 = g.row_ptr[c];
-    dc = g.row_ptr[c + 1] - e0;
+    e0 = ld_graph(g.row_ptr, c);
+    dc = ld_graph(g.row_ptr, c + 1) - e0;
   }
 }
 
@@ -80,7 +80,7 @@ __device__ __forceinline__ void ingest_tile(const GraphDev &g, const float *__re
       int p0, dv;
       var_range<DV>(g, v, p0, dv);
       const float mx = v2c_store(x, x <= 0.0f);
-      for (int j = 0; j < dv; ++j) st.M[g.var_edges[p0 + j] * TW + lane] = mx;
+      for (int j = 0; j < dv; ++j) st.M[ld_graph(g.var_edges, p0 + j) * TW + lane] = mx;
     }
     __syncthreads();
   }

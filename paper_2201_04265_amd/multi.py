@@ -27,12 +27,15 @@ SPLIT_AUTO = 0xFFFFFFFF  # every other code with fewer 64-word tiles than half t
 class Shape(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("slots", ctypes.c_int32 * MAX_CODES), ("refill", ctypes.c_int32),
                 ("stream_codes", ctypes.c_uint32), ("split_codes", ctypes.c_uint32), ("lanes", ctypes.c_int32),
-                ("stream_threads", ctypes.c_int32 * MAX_CODES), ("split_slices", ctypes.c_int32 * MAX_CODES)]
+                ("stream_threads", ctypes.c_int32 * MAX_CODES), ("split_slices", ctypes.c_int32 * MAX_CODES),
+                ("span", ctypes.c_int32 * MAX_CODES)]
 
     @classmethod
     def make(cls, waves=0, slots=None, refill=0, stream_codes=0, split_codes=0, lanes=0, stream_threads=None,
-             split_slices=None):
+             split_slices=None, span=None):
         s = cls()
+        for i, v in enumerate(span or []):
+            s.span[i] = int(v)
         s.waves = int(waves)
         s.refill = int(refill)
         s.lanes = int(lanes)
@@ -49,12 +52,22 @@ class Shape(ctypes.Structure):
     def as_dict(self, ncodes):
         d = {"waves": self.waves, "slots": [self.slots[i] for i in range(ncodes)], "refill": self.refill,
              "lanes": self.lanes, "stream_threads": [self.stream_threads[i] for i in range(ncodes)],
-             "split_slices": [self.split_slices[i] for i in range(ncodes)]}
+             "split_slices": [self.split_slices[i] for i in range(ncodes)],
+             "span": [self.span[i] for i in range(ncodes)]}
         if self.stream_codes:
             d["stream_codes"] = [i for i in range(ncodes) if (self.stream_codes >> i) & 1]
         if self.split_codes:
             d["split_codes"] = [i for i in range(ncodes) if (self.split_codes >> i) & 1]
         return d
+
+
+FAULT_OFFSET = 480  # LDPC_MULTI_FAULT_OFFSET
+
+
+def fault(workspace: torch.Tensor) -> int:
+    """The fault word of the last batched launch on this workspace: nonzero iff a group
+    slot's barrier gave up waiting (its outputs are then invalid).  Synchronises."""
+    return int(workspace[FAULT_OFFSET:FAULT_OFFSET + 4].view(torch.int32).item())
 
 
 class Batch:
@@ -167,7 +180,7 @@ def _signature(graphs, batch: Batch, early_stop) -> str:
         h.update(c.tobytes())
         h.update(v.tobytes())
         h.update(f"{g.m},{g.n},{x.shape[0]},{j.max_iters};".encode())
-    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName};shape-v2".encode())
+    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName};shape-v3".encode())
     return h.hexdigest()
 
 
@@ -200,7 +213,7 @@ def tuned_shape(batch: Batch, early_stop=True, retune=False, persistent_only=Fal
         d = cache[key]
         return Shape.make(d["waves"], d["slots"], d.get("refill", 0), _mask(d.get("stream_codes", [])),
                           _mask(d.get("split_codes", [])), d.get("lanes", 0), d.get("stream_threads"),
-                          d.get("split_slices"))
+                          d.get("split_slices"), d.get("span"))
     best, ms = batch.autotune(early_stop, persistent_only=persistent_only)
     cache[key] = dict(best.as_dict(batch.ncodes), ms=ms)
     try:

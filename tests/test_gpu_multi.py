@@ -218,3 +218,66 @@ def test_orders_with_stream_codes(P, c4):
     out = P.decode_multi(graphs, llrs, 30, True, shape=P.Shape.make(stream_codes=P.STREAM_AUTO), orders=orders)
     torch.cuda.synchronize()
     _same(ref, _np(out))
+
+
+@pytest.mark.parametrize("span,slots,lanes,refill", [(4, 4, 64, 1), (3, 5, 32, 4), (8, 2, 16, 1), (2, 11, 64, 64)])
+def test_group_slots_equal_plain(P, span, slots, lanes, refill):
+    """Slots shared by several workgroups (phases split over them, barriers in global memory)
+    give the plain decoder's outputs bit for bit, with refill, narrow slots and batched refills."""
+    code = W.code("c2")
+    g = P.Graph.from_code(code)
+    wd = W.words("c2", 2, 3, 1.5, 0, 700, fp32=True)
+    x = torch.from_numpy(wd.llr).cuda()
+    ref = _plain(P, [g], [x], 50)
+    batch = P.Batch([g], [x], 50)
+    sh = P.Shape.make(8, [slots], refill, lanes=lanes, span=[span])
+    r, _ = batch.resolve(sh)
+    assert r.span[0] == span and r.slots[0] == slots
+    ws = batch.workspace(sh)
+    batch.run(True, sh, ws)
+    torch.cuda.synchronize()
+    _same(ref, _np(batch.outs))
+    assert P.fault(ws) == 0
+
+
+def test_group_slots_mixed_codes_fixed_iterations(P):
+    """Two codes of different degree profiles (the mixed kernel), group slots, no early stop,
+    one code at zero iterations; the same workspace used twice."""
+    code_a, code_b = W.code("c1"), W.code("c3")
+    ga, gb = P.Graph.from_code(code_a), P.Graph.from_code(code_b)
+    xa = torch.from_numpy(W.words("c1", 1, 0, 2.0, 0, 300, fp32=True).llr).cuda()
+    xb = torch.from_numpy(W.words("c3", 3, 0, 1.5, 0, 70, fp32=True).llr).cuda()
+    for T in ((7, 3), (0, 2)):
+        ref = [_plain(P, [ga], [xa], T[0], False)[0], _plain(P, [gb], [xb], T[1], False)[0]]
+        batch = P.Batch([ga, gb], [xa, xb], list(T))
+        sh = P.Shape.make(16, [2, 2], span=[3, 6])
+        ws = batch.workspace(sh)
+        batch.run(False, sh, ws)
+        torch.cuda.synchronize()
+        _same(ref, _np(batch.outs))
+        assert P.fault(ws) == 0
+
+
+def test_group_slots_beyond_capacity_rejected(P):
+    """Explicit group slots that the GPU cannot hold resident at once are refused before any launch."""
+    g = P.Graph.from_code(W.code("c1"))
+    x = torch.from_numpy(W.words("c1", 1, 0, 2.0, 0, 64 * 64, fp32=True).llr).cuda()
+    batch = P.Batch([g], [x], 20)
+    with pytest.raises(Exception, match="resident"):
+        batch.resolve(P.Shape.make(16, [64], span=[64]))
+
+
+def test_automatic_group_slots_for_few_words_of_a_long_code(P):
+    """A batch of few words of a long code gets group slots automatically; outputs equal plain."""
+    code = W.code("c3")
+    g = P.Graph.from_code(code)
+    x = torch.from_numpy(W.words("c3", 3, 1, 1.5, 0, 130, fp32=True).llr).cuda()
+    batch = P.Batch([g], [x], 30)
+    r, _ = batch.resolve(P.Shape.make(16))
+    assert r.slots[0] == 3 and r.span[0] > 1
+    ref = _plain(P, [g], [x], 30)
+    ws = batch.workspace(P.Shape.make(16))
+    batch.run(True, P.Shape.make(16), ws)
+    torch.cuda.synchronize()
+    _same(ref, _np(batch.outs))
+    assert P.fault(ws) == 0
