@@ -287,7 +287,9 @@ ldpc_status ldpc_plan_destroy(ldpc_plan_t plan);
  * for one code at a time and keeps what is faster (one pass over the codes), then each
  * stream-form code's workgroup size and each split-form code's slices, then the
  * persistent launch's shape (waves per workgroup x slot scale x refill threshold x slot
- * width) when a code uses it.  Every candidate runs three times (the first a warm-up).
+ * width, and halved and quartered automatic spans) when a code uses it, then each persistent
+ * code's span doubled and halved.  Candidates that the launch cannot take (group slots beyond
+ * the resident capacity) are skipped.  Every candidate runs three times (the first a warm-up).
  * Writes the jobs' outputs; allocates and frees its own temporary workspace (the largest
  * any candidate needs).  Synchronises `stream`.
  */

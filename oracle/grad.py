@@ -43,8 +43,10 @@ def _tables(code):
     return chk_tab, var_tab, ci, E
 
 
-def forward_torch(code, llr: torch.Tensor, w: torch.Tensor, tabs=None) -> torch.Tensor:
-    """Posterior L [B, n] of the unrolled weighted form (T = w.shape[0]) in torch FP64."""
+def forward_torch(code, llr: torch.Tensor, w: torch.Tensor, tabs=None, pre_clamp=None) -> torch.Tensor:
+    """Posterior L [B, n] of the unrolled weighted form (T = w.shape[0]) in torch FP64.
+    pre_clamp: optional list that receives, per iteration t >= 1, the v->c sums A^(t+1)
+    [B, E] before the clamp (for choosing test coordinates near or beyond it)."""
     chk_tab, var_tab, var_of_edge, E = tabs or _tables(code)
     B = llr.shape[0]
     T = w.shape[0]
@@ -69,6 +71,8 @@ def forward_torch(code, llr: torch.Tensor, w: torch.Tensor, tabs=None) -> torch.
             excl = (X.unsqueeze(-2) * off_v).sum(-1)  # [B, n, dv]
             A = torch.zeros((B, E), dtype=llr.dtype)
             A[:, vt[vmask]] = (llr.unsqueeze(-1) + excl)[:, vmask]
+            if pre_clamp is not None:
+                pre_clamp.append(A.detach().clone())
             M = torch.clamp(A, -L_MAX, L_MAX)
         th = torch.where(cmask, torch.tanh(M[:, ct.clamp(min=0)] / 2.0), ones)  # [B, m, dc]
         P = torch.where(off_c, th.unsqueeze(-2), ones).prod(-1)  # product over the other edges

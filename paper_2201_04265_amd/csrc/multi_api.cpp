@@ -287,6 +287,18 @@ extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t n
       }
       if (st != LDPC_OK) break;
     }
+    // 4. each code's span, doubled or halved, one code at a time (from the best so far:
+    // codes differ in iterations per word, which the automatic share does not know)
+    for (int q = 0; q < ncodes && st == LDPC_OK; ++q) {
+      if (cur.slots[q] <= 0) continue;
+      const int base_span = std::max(1, cur.span[q]);
+      for (int sp : {2 * base_span, base_span / 2}) {
+        if (sp < 1 || sp > kMaxSpan || sp == base_span) continue;
+        ldpc_multi_shape c = cur;
+        c.span[q] = sp;
+        if ((st = attempt(c)) != LDPC_OK) break;
+      }
+    }
   }
   (void)hipEventDestroy(T.t0);
   (void)hipEventDestroy(T.t1);

@@ -77,29 +77,55 @@ def test_adjoint_matches_reference_gradient(P, c5):
         per = np.abs(a - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
         print("norm rel", err, "per-coord max", per.max())
         assert err <= 1e-3
-        assert per.max() <= 1e-2
+        assert per.max() <= 1e-3
 
 
 def test_adjoint_matches_finite_differences(P, c5):
-    """Central differences of the FP64 C forward on 16 words at sampled weights and LLRs."""
+    """Central differences of the FP64 C forward on 16 words: weights and LLRs sampled at
+    random, weights whose downstream v->c sums sit beyond the +-20 clamp (gradient through
+    them is zero) or just inside it, and the LLRs of the largest magnitude.  Per coordinate
+    within 1e-3 of the difference quotient (floor 1e-3 of the largest), 1e-3 in norm."""
     from oracle import grad
 
     code, g, w = c5
-    wd = W.words("c5", 5, 0, 2.0, 0, 16, fp32=True)
+    B = 16
+    wd = W.words("c5", 5, 0, 2.0, 0, B, fp32=True)
+    llr64, w64 = wd.llr.astype(np.float64), w.astype(np.float64)
     _, _, gl, gw = gpu_grads(P, g, wd.llr, w, wd.cw)
     rng = np.random.default_rng(7)
-    # sample weights on edges of the first iterations and of the last one, LLRs of any word
-    cw_ = [(int(rng.integers(10)), int(rng.integers(code.nnz))) for _ in range(24)]
-    cl_ = [(int(rng.integers(16)), int(rng.integers(code.n))) for _ in range(24)]
-    fw, fl = grad.fd_grad(code, wd.llr.astype(np.float64), w.astype(np.float64), wd.cw, cw_, cl_)
-    aw = np.array([gw[t, e] for t, e in cw_])
-    al = np.array([gl[b, v] for b, v in cl_])
+    T, E = w.shape
+    # A^(t+1) before the clamp, per iteration t >= 1: weight w[t][e] enters the sums of the
+    # other edges of e's variable (the sums of the variable minus edge e itself)
+    pre = []
+    grad.forward_torch(code, torch.from_numpy(llr64), torch.from_numpy(w64), pre_clamp=pre)
+    edge_var = np.asarray(code.indices, dtype=np.int64)  # variable of each edge (CSR edge order)
+    sat = np.zeros((T, E))
+    near = np.zeros((T, E))
+    for t in range(1, T):
+        A = pre[t - 1].numpy()  # [B, E], the sums that w[t-1] feeds
+        per_var_sat = np.zeros(code.n)
+        per_var_near = np.zeros(code.n)
+        np.add.at(per_var_sat, edge_var, (np.abs(A) > 20.5).sum(0))
+        np.add.at(per_var_near, edge_var, ((np.abs(A) > 18.0) & (np.abs(A) < 19.9)).sum(0))
+        sat[t - 1] = per_var_sat[edge_var]
+        near[t - 1] = per_var_near[edge_var]
+    coords_w = [(int(rng.integers(T)), int(rng.integers(E))) for _ in range(32)]
+    for score in (sat, near):
+        top = np.argsort(score.ravel())[::-1][:16]
+        assert score.ravel()[top].min() > 0  # such sums exist at 2.0 dB
+        coords_w += [(int(i // E), int(i % E)) for i in top]
+    coords_l = [(int(rng.integers(B)), int(rng.integers(code.n))) for _ in range(24)]
+    big = np.argsort(np.abs(llr64).ravel())[::-1][:16]
+    coords_l += [(int(i // code.n), int(i % code.n)) for i in big]
+    fw, fl = grad.fd_grad(code, llr64, w64, wd.cw, coords_w, coords_l)
+    aw = np.array([gw[t, e] for t, e in coords_w])
+    al = np.array([gl[b, v] for b, v in coords_l])
     for a, f in ((aw, fw), (al, fl)):
         err = np.linalg.norm(a - f) / np.linalg.norm(f)
         per = np.abs(a - f) / np.maximum(np.abs(f), 1e-3 * np.abs(f).max())
-        print("FD norm rel", err, "per-coord", per.max())
+        print("FD norm rel", err, "per-coord", per.max(), "coords", len(f))
         assert err <= 1e-3
-        assert per.max() <= 1e-2
+        assert per.max() <= 1e-3
 
 
 def test_full_size_deterministic(P, c5):
