@@ -53,14 +53,14 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "3180728838fe588bce53458e489db05a2327cbdb", "bytes_per_launch": 70043147444,
+               "sha1": "e5034eb49e53c7ea7cc8ff01325a1bd7630b1195", "bytes_per_launch": 69824416813,
                "valu_insts_per_launch": 43903465560},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": "9b6a51c4898facfd90ec0fb11645087404a1b474", "bytes_per_launch": 1804775474886},
+              "sha1": "506c342603acf124a2741ad9b26f575bd03c1aaf", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "c8b85da829ed61534d9a6a34bb1635ab1325e217", "bytes_per_launch": 1599788648506,
-                "shape": {"waves": 8, "slots": [768], "refill": 1, "lanes": 64, "stream_threads": [0],
-                          "split_slices": [0]}},
+                "sha1": "32e32b9034e4f197e044b88c59198a7d9e7f88f2", "bytes_per_launch": 1552803762331,
+                "shape": {"waves": 16, "slots": [512], "refill": 1, "lanes": 64, "stream_threads": [0],
+                          "split_slices": [0], "span": [1]}},
 }
 HBM_PEAK_GBS = 8000.0
 MAX_ITERS = 50
@@ -139,6 +139,25 @@ def bytes_per_word_iteration(n: int, E: int) -> int:
 def io_bytes_per_word(n: int) -> int:
     """Channel LLRs in (4 B/bit), posterior (4 B/bit) and hard decision (1 B/bit) out."""
     return 9 * n
+
+
+def copy_ceiling(torch, reps=5):
+    """Achievable HBM bandwidth of this device: a plain 1 GiB device-to-device copy (1 GiB read
+    and 1 GiB written per copy), timed with HIP events after a warm-up copy."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    gbs = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    return {"gb_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "ms_per_copy": ms,
+            "note": "torch device-to-device copy of 1 GiB (2 GiB moved), mean of %d after a warm-up" % reps}
 
 
 def make_inputs(args, torch):
@@ -849,6 +868,7 @@ def main():
         "forms": results,
         "roofline": roofline(head, code, B),
     }
+    result["hbm_copy_ceiling"] = copy_ceiling(torch)
     if generation is not None:
         result["device_generation"] = generation
     if not args.no_cpu_baseline:
