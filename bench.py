@@ -58,8 +58,8 @@ COUNTERS = {
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
               "sha1": "506c342603acf124a2741ad9b26f575bd03c1aaf", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "32e32b9034e4f197e044b88c59198a7d9e7f88f2", "bytes_per_launch": 1552803762331,
-                "shape": {"waves": 16, "slots": [512], "refill": 1, "lanes": 64, "stream_threads": [0],
+                "sha1": "f85e611eee70d3dbb156602229e739786e5b4333", "bytes_per_launch": 1552795182141,
+                "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }
 HBM_PEAK_GBS = 8000.0

@@ -221,7 +221,8 @@ typedef struct {
  * half the GPU's compute units; 0 = none. */
 #define LDPC_SPLIT_AUTO 0xFFFFFFFFu
 /* lanes: words one slot holds at a time (1..64; 0 = 64); a code has at most ceil(batch / lanes)
- * slots.
+ * slots, and at most as many as the GPU holds resident at once (slots beyond that would start
+ * only when the code's queue is empty).
  * stream_threads[q]: workgroup size of code q in the stream form (0 = automatic, else as
  * ldpc_decode_stream's threads); split_slices[q]: workgroups per tile of code q in the split
  * form (0 = automatic, else as ldpc_decode_split's slices).
@@ -289,7 +290,9 @@ ldpc_status ldpc_plan_destroy(ldpc_plan_t plan);
  * persistent launch's shape (waves per workgroup x slot scale x refill threshold x slot
  * width, and halved and quartered automatic spans) when a code uses it, then each persistent
  * code's span doubled and halved.  Candidates that the launch cannot take (group slots beyond
- * the resident capacity) are skipped.  Every candidate runs three times (the first a warm-up).
+ * the resident capacity) are skipped.  Every candidate runs once to warm up and then 2 to 16 times
+ * (about 40 ms in all); its time is the median.  The winner and the automatic start are timed
+ * again at the end, and the faster of the two is returned.
  * Writes the jobs' outputs; allocates and frees its own temporary workspace (the largest
  * any candidate needs).  Synchronises `stream`.
  */

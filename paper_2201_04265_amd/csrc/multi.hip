@@ -435,14 +435,15 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
   auto persistent = [&](int q) { return jobs[q].batch > 0 && !((mask >> q) & 1u); };
   // automatic slot counts: fill the resident capacity, shared in proportion to words x
   // edges; a code whose words fill fewer slots than its share gets group slots (span > 1)
-  bool need_auto = sh.lanes == 0, any_group = false;
+  bool need_auto = sh.lanes == 0, any_group = false, any_persistent = false;
   for (int q = 0; q < ncodes; ++q) {
     if (!persistent(q)) continue;
+    any_persistent = true;
     need_auto |= sh.slots[q] == 0 || sh.span[q] == 0;
     any_group |= sh.span[q] > 1;
   }
   double cap = 0;  // workgroups of this launch the GPU holds resident at once
-  if (need_auto || any_group) {
+  if (any_persistent) {
     int dev = 0, cus = 0;
     LDPC_HIP_CHECK(hipGetDevice(&dev));
     LDPC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -482,6 +483,10 @@ ldpc_status multi_resolve(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc
     } else if (sh.span[q] == 0) {
       sh.span[q] = 1;
     }
+    // a code's slots beyond what the GPU holds resident at once would only start once
+    // its first slots leave, which they do when its queue is empty: they are dropped
+    if (persistent(q) && cap > 0)
+      sh.slots[q] = std::max(1, std::min(sh.slots[q], (int)(cap / std::max(1, sh.span[q]))));
     wgs += (long)sh.slots[q] * sh.span[q];
   }
   if (any_group && wgs > (long)cap) {

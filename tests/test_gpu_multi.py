@@ -259,12 +259,18 @@ def test_group_slots_mixed_codes_fixed_iterations(P):
 
 
 def test_group_slots_beyond_capacity_rejected(P):
-    """Explicit group slots that the GPU cannot hold resident at once are refused before any launch."""
+    """A code's slots are capped at what the GPU holds resident; explicit group slots of several
+    codes that the GPU cannot hold resident at once are refused before any launch."""
     g = P.Graph.from_code(W.code("c1"))
     x = torch.from_numpy(W.words("c1", 1, 0, 2.0, 0, 64 * 64, fp32=True).llr).cuda()
     batch = P.Batch([g], [x], 20)
+    r, _ = batch.resolve(P.Shape.make(16, [64], span=[64]))
+    assert r.span[0] == 64 and 1 <= r.slots[0] < 64  # 16-wave workgroups: at most a few resident per CU
+    cap = r.slots[0] * 64
+    two = P.Batch([g, g], [x, x], 20)
     with pytest.raises(Exception, match="resident"):
-        batch.resolve(P.Shape.make(16, [64], span=[64]))
+        two.resolve(P.Shape.make(16, [r.slots[0], r.slots[0]], span=[64, 64]))
+    assert cap >= 64
 
 
 def test_automatic_group_slots_for_few_words_of_a_long_code(P):
