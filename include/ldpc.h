@@ -235,8 +235,10 @@ typedef struct {
  * sum over codes of slots x span <= resident workgroups of the kernel (automatic spans shrink to
  * fit; explicit ones that do not fit are LDPC_ERR_INVALID_ARG).  The barrier gives up after
  * seconds of waiting (possible only if other work keeps the launch's workgroups from becoming
- * resident that long); the int at byte offset LDPC_MULTI_FAULT_OFFSET of the workspace is then
- * nonzero after the launch and its outputs are invalid. */
+ * resident that long; the environment variable LDPC_GROUP_SPIN_LIMIT, read at each launch, sets
+ * the number of polls instead, for tests of this path); the int at byte offset
+ * LDPC_MULTI_FAULT_OFFSET of the workspace is then nonzero after the launch, and its outputs are
+ * invalid. */
 typedef struct {
   int32_t waves;
   int32_t slots[LDPC_MAX_CODES];

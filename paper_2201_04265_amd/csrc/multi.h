@@ -38,6 +38,7 @@ struct MultiArgs {
   int32_t njobs;
   int32_t refill_min;  // pending lanes that trigger a refill
   int32_t lanes;       // lanes of a slot that take words (the others stay idle)
+  uint32_t spin_limit; // polls before a group barrier gives up
 };
 
 using MultiKernel = void (*)(MultiArgs, int *, int);

@@ -30,6 +30,7 @@
 // (the same masks give the same decisions), so all members take the same branches
 // and meet at the same barriers.
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.h"
 #include "multi.h"
@@ -46,31 +47,37 @@ namespace ldpc {
 // waits for the other members and invalidates its caches (agent-scope acquire: the
 // compute unit's L1 and the L2 copies, for every wavefront of the workgroup, which meets
 // again before reading).  One write-back and one invalidation per workgroup and barrier,
-// not one per wavefront.  The host launches group slots only when every workgroup of the
-// launch can be resident at once, so the wait ends; a wait past kSpinLimit polls
-// (seconds, far beyond any phase) sets the launch's fault word and stops waiting, which
-// the caller can test.
-constexpr unsigned kSpinLimit = 1u << 26;
+// not one per wavefront.
+// The host launches group slots only when every workgroup of the launch can be resident
+// at once, so the wait ends.  It is bounded all the same: after `limit` polls, or as soon
+// as the launch's fault word is set, the barrier fails -- it sets the fault word, and the
+// whole workgroup leaves its slot; the other members' waits then fail too, so the launch
+// ends with the fault word telling the caller that its outputs are invalid.
+constexpr unsigned kSpinLimit = 1u << 21;  // polls of about a microsecond each
 
-__device__ __forceinline__ void group_barrier(int *cnt, int span, int &epoch, int *fault) {
+__device__ __forceinline__ bool group_barrier(int *cnt, int span, int &epoch, int *fault, unsigned limit,
+                                              int *fail_lds) {
   __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads and stores are complete
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const int target = (epoch + 1) * span;
     __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins == kSpinLimit) {
+    int failed = 0;
+    for (unsigned spins = 0; __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
+      if (spins >= limit || __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         __hip_atomic_fetch_or(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        failed = 1;
         break;
       }
+      __builtin_amdgcn_s_sleep(2);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *fail_lds = failed;
   }
   __syncthreads();
   ++epoch;
+  return *fail_lds == 0;
 }
 
 __device__ __forceinline__ int next_word(const MultiJob &J, int w) {
@@ -177,9 +184,9 @@ __device__ __forceinline__ void slot_pass_any(const MultiJob &J, TileState st, c
 // written out and refilled together once at least `refill_min` of them wait or no
 // lane is running.  unsat_w and lane_lds are the workgroup's LDS scratch.
 template <int DC, int DV>
-__device__ void run_slot(const MultiJob &J, int local_slot, int member, int *counter, int *fault, int early_stop,
-                         int refill_min, int lanes, unsigned long long *unsat_w, int *lane_lds, int wave, int W,
-                         int lane, float *psl) {
+__device__ void run_slot(const MultiJob &J, int local_slot, int member, int *counter, int *fault,
+                         unsigned spin_limit, int early_stop, int refill_min, int lanes, unsigned long long *unsat_w,
+                         int *lane_lds, int *fail_lds, int wave, int W, int lane, float *psl) {
   const GraphDev &g = J.g;
   const TileState st = tile_state_block(J.ws + (size_t)local_slot * tile_bytes(g.nnz, g.n), g.nnz, g.n);
   const int span = J.span;
@@ -188,11 +195,14 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int member, int *cou
   int epoch = 0;
   const int gw = member * W + wave, GW = span * W;
   int *lw = group ? sync + kSyncLaneWords : lane_lds;  // lane -> word table of the slot
+  // A failed group barrier (see group_barrier) clears `ok`; the workgroup then stops waiting at
+  // the slot's barriers, finishes the step (its outputs are invalid anyway) and leaves.
+  bool ok = true;
   auto slot_barrier = [&]() {
-    if (group)
-      group_barrier(sync, span, epoch, fault);
-    else
+    if (!group)
       __syncthreads();
+    else if (ok)
+      ok = group_barrier(sync, span, epoch, fault, spin_limit, fail_lds);
   };
 
   if (member == 0 && wave == 0) {  // lanes >= `lanes` never take a word
@@ -207,7 +217,7 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int member, int *cou
   bool pending = false;  // its word has stopped and waits for output
   bool odd = false;      // its last messages are in E1 (else E0)
   int it_lane = 0;
-  if (__ballot(has) == 0ull) return;  // same in every member: nothing left for this slot
+  if (!ok || __ballot(has) == 0ull) return;  // same in every member: nothing left for this slot
   slot_pass_any<DV>(J, st, st.E0, false, false, false, 0, 0, has, word, gw, GW, lane);
   slot_barrier();
 
@@ -266,7 +276,7 @@ __device__ void run_slot(const MultiJob &J, int local_slot, int member, int *cou
       }
     }
     slot_pass_any<DV>(J, st, En, running, out, odd, out_word, out_it, fresh, word, gw, GW, lane);
-    if (__ballot(has) == 0ull) break;  // same value in every wave and member
+    if (!ok || __ballot(has) == 0ull) break;  // same value in every wave and member
     if (running) ++it_lane;
     slot_barrier();
   }
@@ -285,11 +295,13 @@ template <int DC, int DV>
 __device__ __forceinline__ void run_workgroup(const MultiArgs &a, int *counters, int early_stop, float *psl) {
   __shared__ unsigned long long unsat_w[16];
   __shared__ int lane_lds[TW];
+  __shared__ int fail_lds;
   const int q = find_job(a, blockIdx.x);
   const MultiJob &J = a.jobs[q];
   const int local = (int)blockIdx.x - J.wg0;
-  run_slot<DC, DV>(J, local % J.nslots, local / J.nslots, counters + q, counters + kFaultInt, early_stop,
-                   a.refill_min, a.lanes, unsat_w, lane_lds, wave_id(), blockDim.x >> 6, lane_id(), psl);
+  run_slot<DC, DV>(J, local % J.nslots, local / J.nslots, counters + q, counters + kFaultInt,
+                   a.spin_limit, early_stop, a.refill_min, a.lanes, unsat_w, lane_lds,
+                   &fail_lds, wave_id(), blockDim.x >> 6, lane_id(), psl);
 }
 
 template <int DC, int DV>
@@ -523,6 +535,10 @@ ldpc_status multi_args(const ldpc_graph_t *graphs, int32_t ncodes, const ldpc_jo
   a->njobs = ncodes;
   a->refill_min = std::min(sh.refill, sh.lanes > 0 ? sh.lanes : kTile);
   a->lanes = sh.lanes > 0 ? sh.lanes : kTile;
+  // polls before a group barrier gives up; LDPC_GROUP_SPIN_LIMIT overrides the default so
+  // that tests can force the failure path (a small value makes the waits fail at once)
+  a->spin_limit = kSpinLimit;
+  if (const char *e = std::getenv("LDPC_GROUP_SPIN_LIMIT")) a->spin_limit = (uint32_t)std::strtoul(e, nullptr, 10);
   int wg = 0;
   for (int q = 0; q < ncodes; ++q) {
     MultiJob &J = a->jobs[q];

@@ -287,3 +287,25 @@ def test_automatic_group_slots_for_few_words_of_a_long_code(P):
     torch.cuda.synchronize()
     _same(ref, _np(batch.outs))
     assert P.fault(ws) == 0
+
+
+def test_group_barrier_failure_is_reported_and_recovered(P, monkeypatch):
+    """The group barriers' bounded wait forced to give up at once (a limit of 0 polls, set from
+    the host): the launch still ends, the workspace's fault word reports it, and the next launch
+    with the default limit is correct again."""
+    code = W.code("c2")
+    g = P.Graph.from_code(code)
+    x = torch.from_numpy(W.words("c2", 2, 4, 2.0, 0, 300, fp32=True).llr).cuda()
+    ref = _plain(P, [g], [x], 50)
+    batch = P.Batch([g], [x], 50)
+    sh = P.Shape.make(8, [3], span=[4])
+    ws = batch.workspace(sh)
+    monkeypatch.setenv("LDPC_GROUP_SPIN_LIMIT", "0")
+    batch.run(True, sh, ws)
+    torch.cuda.synchronize()
+    assert P.fault(ws) != 0
+    monkeypatch.delenv("LDPC_GROUP_SPIN_LIMIT")
+    batch.run(True, sh, ws)
+    torch.cuda.synchronize()
+    assert P.fault(ws) == 0
+    _same(ref, _np(batch.outs))
