@@ -58,7 +58,7 @@ COUNTERS = {
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
               "sha1": "506c342603acf124a2741ad9b26f575bd03c1aaf", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "f85e611eee70d3dbb156602229e739786e5b4333", "bytes_per_launch": 1552795182141,
+                "sha1": "6c017051ea124975fe5903c21c2bd3683781f5df", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }
