@@ -53,12 +53,12 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "e5034eb49e53c7ea7cc8ff01325a1bd7630b1195", "bytes_per_launch": 69824416813,
-               "valu_insts_per_launch": 43903465560},
+               "sha1": "8d7cd3d80dfea3e8575e8caeb5c3d8dc71b5ccfd", "bytes_per_launch": 66272928473,
+               "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": "506c342603acf124a2741ad9b26f575bd03c1aaf", "bytes_per_launch": 1804880054051},
+              "sha1": "553e8c305883cbd92f4b157136f0fe103205e80f", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "6c017051ea124975fe5903c21c2bd3683781f5df", "bytes_per_launch": 1552948885069,
+                "sha1": "fe6a843d26078942544ecb62d2fb8d81a709975b", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }

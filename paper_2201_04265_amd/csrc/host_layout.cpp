@@ -103,6 +103,12 @@ ldpc_status graph_build_host(int32_t m, int32_t n, ldpc_format fmt, const int32_
 // any result.  For quasi-cyclic codes the stable sort keeps each block row's checks
 // consecutive and 64-aligned, so the 64 variables a wavefront updates (consecutive
 // columns of one circulant) also reach 64 distinct banks.
+// The wavefronts of the kernel take these groups, and the groups of 64 consecutive
+// variables, from a shared counter, so the tables list both costliest first (largest
+// degree; ties in index order): taken in that order by whichever wavefront is free,
+// the work of a phase spreads over the wavefronts as in longest-first list scheduling,
+// whatever the workgroup size.  Which wavefront updates a check or a variable changes
+// no result either.
 StreamGroupLayout stream_group_layout(const GraphHost *g) {
   StreamGroupLayout L;
   const int m = g->m;
@@ -127,6 +133,23 @@ StreamGroupLayout stream_group_layout(const GraphHost *g) {
     start += gi + 1 < groups ? 64 * (int64_t)dmax : 64 * (int64_t)(dmax - 1) + cnt;
   }
   L.floats = start;
+  // costliest first: the groups of checks (formed in ascending degree) and of variables
+  auto costliest_first = [](const std::vector<int32_t> &deg) {
+    std::vector<int32_t> order(deg.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    return order;
+  };
+  std::vector<int32_t> cdeg(groups, 0);
+  for (size_t s = 0; s < L.slot.size(); ++s) cdeg[s / 64] = std::max(cdeg[s / 64], L.slot[s] >> 16);
+  const std::vector<int32_t> corder = costliest_first(cdeg);
+  std::vector<int32_t> formed = L.slot;
+  for (int gi = 0; gi < groups; ++gi)
+    std::copy(formed.begin() + 64 * (size_t)corder[gi], formed.begin() + 64 * (size_t)(corder[gi] + 1),
+              L.slot.begin() + 64 * (size_t)gi);
+  std::vector<int32_t> vdeg((g->n + 63) / 64, 0);
+  for (int v = 0; v < g->n; ++v) vdeg[v >> 6] = std::max(vdeg[v >> 6], g->var_ptr[v + 1] - g->var_ptr[v]);
+  L.var_order = costliest_first(vdeg);
   return L;
 }
 

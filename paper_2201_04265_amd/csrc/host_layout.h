@@ -62,8 +62,10 @@ inline int32_t kernel_kind(const GraphHost *g) {
 
 // Stream form, runtime check degrees: LDS placement of the checks' rows, 64 at a time.
 struct StreamGroupLayout {
-  std::vector<int32_t> slot;  // [64 x groups]: start float | degree << 16 (0 = no check)
-  std::vector<int32_t> pos;   // [nnz]: float index of each edge (CSR order)
+  std::vector<int32_t> slot;       // [64 x groups]: start float | degree << 16 (0 = no check),
+                                   // groups listed by descending degree
+  std::vector<int32_t> pos;        // [nnz]: float index of each edge (CSR order)
+  std::vector<int32_t> var_order;  // [ceil(n / 64)]: groups of 64 variables, costliest first
   int64_t floats = 0;
 };
 StreamGroupLayout stream_group_layout(const GraphHost *g);

@@ -6,9 +6,10 @@
 // LDS barrier, so here a workgroup owns one word at a time: its threads take
 // the checks (check phase) and then the variables (variable phase), in the
 // interleaved order of Algorithm 1 (check c and variable v on thread c mod NT and
-// v mod NT), and every message stays in LDS.  Workgroups are persistent and take
-// the next word from an atomic counter when theirs stops, so a word that needs
-// few iterations never waits for another.
+// v mod NT; for runtime degrees the wavefronts take groups of 64 checks or variables,
+// costliest first, from a counter per phase), and every message stays in LDS.
+// Workgroups are persistent and take the next word from an atomic counter when
+// theirs stops, so a word that needs few iterations never waits for another.
 //
 // LDS per word:
 //   X [nnz] FP32  one message per edge, updated in place: the check phase reads the
@@ -33,7 +34,8 @@
 namespace ldpc {
 
 // X at LDS address 0 (so an edge's byte offset is its LDS address), then the word
-// index and the per-wave syndrome flags.
+// index, the two work counters of the runtime-degree phases and the per-wave syndrome
+// flags.
 inline size_t stream_x_bytes(const ldpc_graph_s *g) { return ((size_t)g->stream_x_floats * 4 + 15) & ~size_t(15); }
 inline size_t stream_lds_bytes(const ldpc_graph_s *g) { return stream_x_bytes(g) + 80; }
 
@@ -55,13 +57,28 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
   float *X = smem;
   int *s_misc = (int *)((char *)smem + xbytes);
   int &s_word = s_misc[0];
+  int *s_next = s_misc + 1;   // [2] runtime degrees: next group of the check / variable phase
   int *s_unsat = s_misc + 4;  // [16] per wavefront: some check of the word is unsatisfied
   const int t = threadIdx.x, NT = blockDim.x;
   const int wave = wave_id(), W = NT >> 6;
   const size_t n = (size_t)g.n;
 
+  // Runtime degrees: a wavefront takes the next group of 64 checks (variables) from the
+  // phase's counter; the tables list the groups costliest first (stream_group_layout).
+  // Each counter is cleared by thread 0 in the other phase, between the barriers that
+  // end its own phases, so no wavefront reads it meanwhile.
+  auto next_group = [&](int *ctr) {
+    int k = 0;
+    if ((t & 63) == 0) k = atomicAdd(ctr, 1);
+    return __builtin_amdgcn_readfirstlane(k);
+  };
+
   for (;;) {
-    if (t == 0) s_word = atomicAdd(counter, 1);
+    if (t == 0) {
+      s_word = atomicAdd(counter, 1);
+      s_next[0] = 0;
+      s_next[1] = 0;
+    }
     lds_barrier();
     const int word = s_word;
     if (word >= B) break;  // same value in every thread
@@ -94,8 +111,11 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         }
       } else {
         // one check per slot (a multiple of 64 slots; empty ones have degree 0), in place
-        // on its interleaved row, which also holds half of the prefix pairs
-        for (int sl = t; sl < xslots; sl += NT) {
+        // on its interleaved row, which also holds half of the prefix pairs; whole groups
+        // of 64 slots, one per wavefront pass, taken from the check phase's counter
+        if (t == 0) s_next[1] = 0;
+        for (int k = next_group(s_next); k < (xslots >> 6); k = next_group(s_next)) {
+          const int sl = (k << 6) | (t & 63);
           const uint32_t info = (uint32_t)xslot[sl];
           const int dc = (int)(info >> 16);
           float *row = X + (info & 0xffffu);
@@ -200,8 +220,38 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         }
         if (v < g.n) update(v, fa);
         if (v + NT < g.n) update(v + NT, fb);
+      } else if constexpr (DV < 0) {
+        // groups of 64 variables from the variable phase's counter, in the order of the
+        // table after the check slots; the reads of the next group are issued before the
+        // update of the current one (two register sets: a third one of up to 16 offsets
+        // would spill)
+        if (t == 0) s_next[0] = 0;
+        const int32_t *__restrict__ vorder = xslot + xslots;
+        const int vgroups = (g.n + 63) >> 6;
+        auto var_of = [&](int k) { return (ld_graph(vorder, (size_t)k) << 6) | (t & 63); };
+        VarIn fa, fb;
+        int ka = next_group(s_next + 1), va = 0, vb = 0;
+        if (ka < vgroups) {
+          va = var_of(ka);
+          if (va < g.n) fetch(va, fa);
+        }
+        while (ka < vgroups) {
+          const int kb = next_group(s_next + 1);
+          if (kb < vgroups) {
+            vb = var_of(kb);
+            if (vb < g.n) fetch(vb, fb);
+          }
+          if (va < g.n) update(va, fa);
+          if (kb >= vgroups) break;
+          ka = next_group(s_next + 1);
+          if (ka < vgroups) {
+            va = var_of(ka);
+            if (va < g.n) fetch(va, fa);
+          }
+          if (vb < g.n) update(vb, fb);
+        }
       } else {
-        // two sets (for runtime degrees a third one of up to 16 offsets would spill)
+        // two sets (the higher fixed degrees would lose resident waves to a third)
         VarIn fa, fb;
         if (t < g.n) fetch(t, fa);
         int v = t;
@@ -299,11 +349,14 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
         return set_error(LDPC_ERR_DEVICE, "stream layout size disagrees with the graph's LDS size");
       off.resize((size_t)g->nnz);
       for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g->var_edges[p]] * 4;
+      // one table: the check slots, then the order of the variable groups
+      std::vector<int32_t> tab(L.slot);
+      tab.insert(tab.end(), L.var_order.begin(), L.var_order.end());
       if (!g->d_xslot) {
-        LDPC_HIP_CHECK(hipMalloc((void **)&g->d_xslot, L.slot.size() * sizeof(int32_t)));
+        LDPC_HIP_CHECK(hipMalloc((void **)&g->d_xslot, tab.size() * sizeof(int32_t)));
         g->stream_slots = (int32_t)L.slot.size();
       }
-      LDPC_HIP_CHECK(hipMemcpy(g->d_xslot, L.slot.data(), L.slot.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      LDPC_HIP_CHECK(hipMemcpy(g->d_xslot, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     LDPC_HIP_CHECK(hipMemcpy(g->d_var_xoff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }

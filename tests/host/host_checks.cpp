@@ -2,6 +2,7 @@
 // the address and undefined-behaviour sanitizers by tests/test_host_sanitizers.py.  Every
 // check is a property the layouts must have, on seeded random parity-check matrices.
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -88,6 +89,30 @@ static void check_layouts(const GraphHost &g) {
         if (L.slot[s] && (L.slot[s] & 0xffff) == L.pos[e0] && (L.slot[s] >> 16) == d) ++hits;
       CHECK(hits == 1);
     }
+    // the groups of 64 slots by non-increasing largest degree
+    const size_t groups = L.slot.size() / 64;
+    int prev = INT_MAX;
+    for (size_t gi = 0; gi < groups; ++gi) {
+      int d = 0;
+      for (int l = 0; l < 64; ++l) d = std::max(d, L.slot[64 * gi + l] >> 16);
+      CHECK(d <= prev);
+      prev = d;
+    }
+    // the groups of 64 variables: a permutation, by non-increasing largest degree
+    const int vgroups = (g.n + 63) / 64;
+    CHECK((int)L.var_order.size() == vgroups);
+    std::vector<int> taken(vgroups, 0);
+    prev = INT_MAX;
+    for (int32_t k : L.var_order) {
+      CHECK(k >= 0 && k < vgroups);
+      if (k < 0 || k >= vgroups) continue;
+      ++taken[k];
+      int d = 0;
+      for (int v = 64 * k; v < std::min(g.n, 64 * k + 64); ++v) d = std::max(d, g.var_ptr[v + 1] - g.var_ptr[v]);
+      CHECK(d <= prev);
+      prev = d;
+    }
+    for (int x : taken) CHECK(x == 1);
   } else {
     const std::vector<int32_t> off = stream_edge_offsets(&g);
     CHECK((int64_t)off.size() == g.nnz && stream_x_floats(&g) == g.nnz);
