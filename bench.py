@@ -53,12 +53,12 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "8d7cd3d80dfea3e8575e8caeb5c3d8dc71b5ccfd", "bytes_per_launch": 66272928473,
+               "sha1": "6e1126dcf65240ca53322f9d73435cdb3d64716d", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": "553e8c305883cbd92f4b157136f0fe103205e80f", "bytes_per_launch": 1804880054051},
+              "sha1": "5ae99b4c9e0cd5b731e4feb1809a89b4d8fcaec0", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "fe6a843d26078942544ecb62d2fb8d81a709975b", "bytes_per_launch": 1552948885069,
+                "sha1": "c0d758fa0b65ca1baada7914cf28bce819926423", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }

@@ -18,7 +18,7 @@ struct ldpc_graph_s : GraphHost {
   int32_t *d_var_xoff = nullptr;  // stream form: LDS byte offsets of the edges (var_edges order)
   int64_t stream_x_floats = 0;     // stream form: floats of a word's message array in LDS
   int32_t *d_xslot = nullptr;      // stream form, runtime degrees: start | degree << 16 per check
-                                   // slot, then the order of the groups of 64 variables
+                                   // slot, then the variable groups' order and edge offsets
   int32_t stream_slots = 0;        // check slots in d_xslot (a multiple of 64)
   // Launch facts of the stream form, filled once on its first call (stream.hip).
   std::mutex stream_mu;

@@ -226,28 +226,34 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         // update of the current one (two register sets: a third one of up to 16 offsets
         // would spill)
         if (t == 0) s_next[0] = 0;
+        // (position k of the order holds the group's index, where its rows start in the
+        // table and its degree when all its variables share one, else -1; the rows are the
+        // 64 lanes' degrees, then entry j of every lane's edge offsets, each read by the
+        // wavefront as one contiguous 256-byte segment)
         const int32_t *__restrict__ vorder = xslot + xslots;
         const int vgroups = (g.n + 63) >> 6;
-        auto var_of = [&](int k) { return (ld_graph(vorder, (size_t)k) << 6) | (t & 63); };
+        auto fetch_group = [&](int k, int &v, VarIn &f) {
+          v = (ld_graph(vorder, (size_t)3 * k) << 6) | (t & 63);
+          if (v >= g.n) return;
+          const int32_t *__restrict__ ve = xslot + ld_graph(vorder, (size_t)3 * k + 1) + (t & 63);
+          const int ud = ld_graph(vorder, (size_t)3 * k + 2);
+          f.dv = ud >= 0 ? ud : ve[0];
+          f.r = F64 ? (float)*(const double *)((const char *)lrow64 + (uint32_t)v * 8u)
+                    : *(const float *)((const char *)lrow32 + (uint32_t)v * 4u);
+#pragma unroll
+          for (int j = 0; j < DVM; ++j)
+            if (j < f.dv) f.off[j] = ve[(j + 1) << 6];
+        };
         VarIn fa, fb;
         int ka = next_group(s_next + 1), va = 0, vb = 0;
-        if (ka < vgroups) {
-          va = var_of(ka);
-          if (va < g.n) fetch(va, fa);
-        }
+        if (ka < vgroups) fetch_group(ka, va, fa);
         while (ka < vgroups) {
           const int kb = next_group(s_next + 1);
-          if (kb < vgroups) {
-            vb = var_of(kb);
-            if (vb < g.n) fetch(vb, fb);
-          }
+          if (kb < vgroups) fetch_group(kb, vb, fb);
           if (va < g.n) update(va, fa);
           if (kb >= vgroups) break;
           ka = next_group(s_next + 1);
-          if (ka < vgroups) {
-            va = var_of(ka);
-            if (va < g.n) fetch(va, fa);
-          }
+          if (ka < vgroups) fetch_group(ka, va, fa);
           if (vb < g.n) update(vb, fb);
         }
       } else {
@@ -349,9 +355,32 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
         return set_error(LDPC_ERR_DEVICE, "stream layout size disagrees with the graph's LDS size");
       off.resize((size_t)g->nnz);
       for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g->var_edges[p]] * 4;
-      // one table: the check slots, then the order of the variable groups
+      // one table: the check slots; then per position of the variable groups' order the
+      // group, where its rows start and its degree when all its variables share one (else
+      // -1); then the rows, group by group: the 64 lanes' degrees, then their edges'
+      // offsets, entry j of lane l at start + 64 (j + 1) + l (64 x (1 + the group's largest
+      // degree) entries)
       std::vector<int32_t> tab(L.slot);
-      tab.insert(tab.end(), L.var_order.begin(), L.var_order.end());
+      const size_t vgroups = L.var_order.size();
+      tab.resize(tab.size() + 3 * vgroups);
+      for (size_t i = 0; i < vgroups; ++i) {
+        const int k = L.var_order[i], v0 = 64 * k, v1 = std::min(g->n, v0 + 64);
+        int gd = 0, gmin = INT32_MAX;
+        for (int v = v0; v < v1; ++v) {
+          gd = std::max(gd, g->var_ptr[v + 1] - g->var_ptr[v]);
+          gmin = std::min(gmin, g->var_ptr[v + 1] - g->var_ptr[v]);
+        }
+        const size_t start = tab.size();
+        tab[L.slot.size() + 3 * i] = k;
+        tab[L.slot.size() + 3 * i + 1] = (int32_t)start;
+        tab[L.slot.size() + 3 * i + 2] = gmin == gd ? gd : -1;
+        tab.resize(start + 64 * (size_t)(gd + 1), 0);
+        for (int v = v0; v < v1; ++v) {
+          tab[start + (v & 63)] = g->var_ptr[v + 1] - g->var_ptr[v];
+          for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p)
+            tab[start + 64 * (size_t)(p - g->var_ptr[v] + 1) + (v & 63)] = off[(size_t)p];
+        }
+      }
       if (!g->d_xslot) {
         LDPC_HIP_CHECK(hipMalloc((void **)&g->d_xslot, tab.size() * sizeof(int32_t)));
         g->stream_slots = (int32_t)L.slot.size();
