@@ -69,8 +69,11 @@ def test_fixed_and_zero_iterations(P):
         same(a, b)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("seed", range(3))
-def test_irregular_codes(P, oracle_lib, seed):
+def test_irregular_codes(P, oracle_lib, seed, dtype):
+    """Runtime-degree codes (mixed degrees inside the groups of 64 checks and variables, n and m
+    not multiples of 64) with FP32 and FP64 channel LLRs: bit-identical to the plain decoder."""
     rng = np.random.default_rng(900 + seed)
     n = int(rng.integers(60, 400))
     m = int(rng.integers(n // 4, n // 2))
@@ -82,7 +85,7 @@ def test_irregular_codes(P, oracle_lib, seed):
         var += list(vs)
     code = codes.from_edges(m, n, np.array(chk), np.array(var))
     g = P.Graph.from_code(code)
-    llr = rng.normal(2.0, 2.0, size=(int(rng.integers(1, 300)), n)).astype(np.float32)
+    llr = rng.normal(2.0, 2.0, size=(int(rng.integers(1, 300)), n)).astype(dtype)
     a, b = both(P, g, llr, 15)
     same(a, b)
 
