@@ -53,7 +53,7 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "6e1126dcf65240ca53322f9d73435cdb3d64716d", "bytes_per_launch": 66162809745,
+               "sha1": "e87ddaab505b38f15c16c86c95383a7a85ff4c8c", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
               "sha1": "5ae99b4c9e0cd5b731e4feb1809a89b4d8fcaec0", "bytes_per_launch": 1804880054051},

@@ -153,6 +153,32 @@ StreamGroupLayout stream_group_layout(const GraphHost *g) {
   return L;
 }
 
+std::vector<int32_t> stream_group_table(const GraphHost *g, const StreamGroupLayout &L,
+                                        const std::vector<int32_t> &var_off) {
+  std::vector<int32_t> tab(L.slot);
+  const size_t vgroups = L.var_order.size();
+  tab.resize(tab.size() + 3 * vgroups);
+  for (size_t i = 0; i < vgroups; ++i) {
+    const int k = L.var_order[i], v0 = 64 * k, v1 = std::min(g->n, v0 + 64);
+    int gd = 0, gmin = INT32_MAX;
+    for (int v = v0; v < v1; ++v) {
+      gd = std::max(gd, g->var_ptr[v + 1] - g->var_ptr[v]);
+      gmin = std::min(gmin, g->var_ptr[v + 1] - g->var_ptr[v]);
+    }
+    const size_t start = tab.size();
+    tab[L.slot.size() + 3 * i] = k;
+    tab[L.slot.size() + 3 * i + 1] = (int32_t)start;
+    tab[L.slot.size() + 3 * i + 2] = gmin == gd ? gd : -1;
+    tab.resize(start + 64 * (size_t)(gd + 1), 0);
+    for (int v = v0; v < v1; ++v) {
+      tab[start + (v & 63)] = g->var_ptr[v + 1] - g->var_ptr[v];
+      for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p)
+        tab[start + 64 * (size_t)(p - g->var_ptr[v] + 1) + (v & 63)] = var_off[(size_t)p];
+    }
+  }
+  return tab;
+}
+
 // Where the check rows sit in LDS.  For a fixed check degree any order of the rows
 // gives the same results (each check reads and writes only its own row), so the rows
 // are placed in the order that keeps the LDS banks of the 64 variables a wavefront

@@ -355,32 +355,7 @@ ldpc_status stream_prepare(ldpc_graph_s *g, StreamKernel k, int max_threads, siz
         return set_error(LDPC_ERR_DEVICE, "stream layout size disagrees with the graph's LDS size");
       off.resize((size_t)g->nnz);
       for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g->var_edges[p]] * 4;
-      // one table: the check slots; then per position of the variable groups' order the
-      // group, where its rows start and its degree when all its variables share one (else
-      // -1); then the rows, group by group: the 64 lanes' degrees, then their edges'
-      // offsets, entry j of lane l at start + 64 (j + 1) + l (64 x (1 + the group's largest
-      // degree) entries)
-      std::vector<int32_t> tab(L.slot);
-      const size_t vgroups = L.var_order.size();
-      tab.resize(tab.size() + 3 * vgroups);
-      for (size_t i = 0; i < vgroups; ++i) {
-        const int k = L.var_order[i], v0 = 64 * k, v1 = std::min(g->n, v0 + 64);
-        int gd = 0, gmin = INT32_MAX;
-        for (int v = v0; v < v1; ++v) {
-          gd = std::max(gd, g->var_ptr[v + 1] - g->var_ptr[v]);
-          gmin = std::min(gmin, g->var_ptr[v + 1] - g->var_ptr[v]);
-        }
-        const size_t start = tab.size();
-        tab[L.slot.size() + 3 * i] = k;
-        tab[L.slot.size() + 3 * i + 1] = (int32_t)start;
-        tab[L.slot.size() + 3 * i + 2] = gmin == gd ? gd : -1;
-        tab.resize(start + 64 * (size_t)(gd + 1), 0);
-        for (int v = v0; v < v1; ++v) {
-          tab[start + (v & 63)] = g->var_ptr[v + 1] - g->var_ptr[v];
-          for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p)
-            tab[start + 64 * (size_t)(p - g->var_ptr[v] + 1) + (v & 63)] = off[(size_t)p];
-        }
-      }
+      const std::vector<int32_t> tab = stream_group_table(g, L, off);
       if (!g->d_xslot) {
         LDPC_HIP_CHECK(hipMalloc((void **)&g->d_xslot, tab.size() * sizeof(int32_t)));
         g->stream_slots = (int32_t)L.slot.size();

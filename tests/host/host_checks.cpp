@@ -113,6 +113,31 @@ static void check_layouts(const GraphHost &g) {
       prev = d;
     }
     for (int x : taken) CHECK(x == 1);
+    // the kernel's table: the slots, the order entries, and the rows of every variable group
+    std::vector<int32_t> off((size_t)g.nnz);
+    for (size_t p = 0; p < off.size(); ++p) off[p] = L.pos[(size_t)g.var_edges[p]] * 4;
+    const std::vector<int32_t> tab = stream_group_table(&g, L, off);
+    const size_t S = L.slot.size();
+    CHECK(tab.size() >= S + 3 * (size_t)vgroups);
+    for (size_t s = 0; s < S; ++s) CHECK(tab[s] == L.slot[s]);
+    size_t end = S + 3 * (size_t)vgroups;
+    for (int i = 0; i < vgroups; ++i) {
+      const int k = tab[S + 3 * i], start = tab[S + 3 * i + 1], ud = tab[S + 3 * i + 2];
+      CHECK(k == L.var_order[i]);
+      CHECK((size_t)start == end);  // rows follow each other in the order's sequence
+      int gd = 0, gmin = INT_MAX;
+      for (int v = 64 * k; v < std::min(g.n, 64 * k + 64); ++v) {
+        const int d = g.var_ptr[v + 1] - g.var_ptr[v];
+        gd = std::max(gd, d);
+        gmin = std::min(gmin, d);
+        CHECK(tab[(size_t)start + (v & 63)] == d);
+        for (int j = 0; j < d; ++j)
+          CHECK(tab[(size_t)start + 64 * (j + 1) + (v & 63)] == off[(size_t)g.var_ptr[v] + j]);
+      }
+      CHECK(ud == (gmin == gd ? gd : -1));
+      end = (size_t)start + 64 * (size_t)(gd + 1);
+    }
+    CHECK(tab.size() == end);
   } else {
     const std::vector<int32_t> off = stream_edge_offsets(&g);
     CHECK((int64_t)off.size() == g.nnz && stream_x_floats(&g) == g.nnz);
