@@ -53,12 +53,12 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "e87ddaab505b38f15c16c86c95383a7a85ff4c8c", "bytes_per_launch": 66162809745,
+               "sha1": "83b487ddc6801e9725c89f901567de1433e6c5d6", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
               "sha1": "5ae99b4c9e0cd5b731e4feb1809a89b4d8fcaec0", "bytes_per_launch": 1804880054051},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "c0d758fa0b65ca1baada7914cf28bce819926423", "bytes_per_launch": 1552948885069,
+                "sha1": "224de4202dc7fe4b9a582c86dec265ec8e3a05ea", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }

@@ -86,7 +86,11 @@ ldpc_status ldpc_graph_info(ldpc_graph_t g, int32_t *m, int32_t *n, int64_t *edg
 /* Host copies of the edge numbering: check_of_edge[e], var_of_edge[e] for e < edges (either may be NULL). */
 ldpc_status ldpc_graph_edges(ldpc_graph_t g, int32_t *check_of_edge, int32_t *var_of_edge);
 
-/* Device bytes ldpc_decode needs as workspace for this graph and batch. */
+/* Device workspace bytes for ldpc_decode at full speed on the current device: 256 bytes plus
+ * one 64-word tile state (the messages of 64 words) per workgroup the device holds resident at
+ * once with ldpc_decode's launch shape, at most one per tile of the batch.  Workgroups take
+ * tiles from a counter and reuse their tile state, so a smaller workspace (at least 256 bytes
+ * plus one tile state) also works, with fewer tiles in flight. */
 ldpc_status ldpc_decode_workspace_size(ldpc_graph_t g, int32_t batch, uint32_t flags, size_t *bytes);
 
 /*
@@ -97,8 +101,9 @@ ldpc_status ldpc_decode_workspace_size(ldpc_graph_t g, int32_t batch, uint32_t f
  * whose decisions satisfy H z^T = 0 (t = 0 tests the channel decisions); its
  * outputs are those of iteration t.  Otherwise every word runs max_iters.
  * max_iters = 0 returns the channel LLRs.  batch = 0 is a no-op.
- * workspace: device, >= ldpc_decode_workspace_size bytes, 256-byte aligned;
- * its contents need no initialisation and are garbage afterwards.
+ * workspace: device, 256-byte aligned, ldpc_decode_workspace_size bytes for full speed and
+ * at least 256 bytes plus one tile state (LDPC_ERR_INVALID_ARG below that); its contents need
+ * no initialisation and are garbage afterwards.
  */
 ldpc_status ldpc_decode(ldpc_graph_t g, const void *llr, int32_t batch, int32_t max_iters, int32_t early_stop,
                         uint32_t flags, uint8_t *hard_bits, float *posterior, int32_t *iters_used, void *workspace,
@@ -128,9 +133,11 @@ ldpc_status ldpc_decode_ex(ldpc_graph_t g, const void *llr, int32_t batch, int32
  * tile state lives in a fixed device array of LDPC_NOALLOC_SCRATCH_BYTES that the
  * library holds on each GPU it runs on until the process ends.  Same arguments (minus
  * the workspace), outputs (bit for bit), and errors as ldpc_decode, plus
- * LDPC_ERR_INVALID_ARG when the batch's tile state (ldpc_decode_workspace_size) exceeds
- * the array: at most floor(LDPC_NOALLOC_SCRATCH_BYTES / tile bytes) x 64 words per call
- * (about 384 words of a (3,6) n=4096 code, 17 000 of an n=96 code).  The first call on
+ * LDPC_ERR_INVALID_ARG when the workspace ldpc_decode would take at full speed
+ * (ldpc_decode_workspace_size) exceeds the array: for codes whose resident workgroups' tile
+ * states fill more than the array, at most floor((LDPC_NOALLOC_SCRATCH_BYTES - 256) / tile
+ * bytes) x 64 words per call (384 words of a (3,6) n=4096 code, 17 472 of an n=96 code); any
+ * batch of a code small enough that they do not.  The first call on
  * a device looks up that device's copy of the array (hipGetSymbolAddress); no call
  * allocates or frees memory.  Every call on a GPU uses the same array: calls that
  * overlap on one GPU (different streams, or different threads) race and must be

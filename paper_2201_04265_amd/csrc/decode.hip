@@ -1,10 +1,13 @@
-// Plain flooding sum-product decoder: one workgroup per 64-word tile.
+// Plain flooding sum-product decoder: one workgroup per 64-word tile at a time.
 //
 // The batch is cut into tiles of 64 words (the batch split of Sec. III-C: every
 // worker decodes whole words).  A workgroup of W wavefronts owns one tile for the
-// whole decode; its waves split the checks and the variables of the graph in the
-// interleaved way of Algorithm 1 (check c and variable v go to wave c mod W and
-// v mod W), with a workgroup barrier where Algorithm 1 exchanges messages.
+// whole decode of that tile; its waves split the checks and the variables of the
+// graph in the interleaved way of Algorithm 1 (check c and variable v go to wave
+// c mod W and v mod W), with a workgroup barrier where Algorithm 1 exchanges messages.
+// Workgroups take tiles from a counter and keep one tile state each in the workspace,
+// reused from tile to tile, so the workspace holds as many tile states as workgroups
+// run at once (at most one per tile), not one per tile of the batch.
 //
 // HBM state of a tile (all FP32 [index][64]):
 //   M  [nnz]  v->c messages (Eq. 6, clamped), stored as M / 16 with the decision z_v
@@ -33,23 +36,18 @@
 namespace ldpc {
 
 template <int DC, int DV>
-__device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__restrict__ llr32,
+__device__ __forceinline__ void plain_decode_tile(GraphDev g, const float *__restrict__ llr32,
                                                   const double *__restrict__ llr64, int B, int max_iters,
-                                                  int early_stop, char *ws, uint8_t *__restrict__ hard,
-                                                  float *__restrict__ post, int32_t *__restrict__ iters,
-                                                  const float *__restrict__ init_cv, float *__restrict__ final_cv) {
-  __shared__ float stage[TW][TW + 1];
-  __shared__ unsigned long long unsat_w[16];
-  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
-  __shared__ float psl_buf[kPsl > 0 ? 16 * kPsl : 1];
+                                                  int early_stop, int tile, const TileState &st,
+                                                  uint8_t *__restrict__ hard, float *__restrict__ post,
+                                                  int32_t *__restrict__ iters, const float *__restrict__ init_cv,
+                                                  float *__restrict__ final_cv, float (*stage)[TW + 1],
+                                                  unsigned long long *unsat_w, float *psl) {
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x >> 6;
-  float *psl = kPsl > 0 ? psl_buf + wave * kPsl : nullptr;
-  const int tile = blockIdx.x;
   const int cw0 = tile * TW;
   const int nvalid = min(TW, B - cw0);
-  const TileState st = tile_state_block(ws + (size_t)tile * tile_bytes(g.nnz, g.n), g.nnz, g.n);
 
   ingest_tile<DV>(g, llr32, llr64, cw0, nvalid, st, stage, wave, W, lane);
   if (init_cv) {
@@ -100,6 +98,41 @@ __device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__res
   if (wave == 0 && lane < nvalid) iters[cw0 + lane] = my_iters;
 }
 
+// Workspace: the tile counter in its first 256 bytes, then one tile state per workgroup.
+constexpr size_t kPlainHeader = 256;
+
+template <int DC, int DV>
+__device__ __forceinline__ void plain_decode_body(GraphDev g, const float *__restrict__ llr32,
+                                                  const double *__restrict__ llr64, int B, int max_iters,
+                                                  int early_stop, char *ws, uint8_t *__restrict__ hard,
+                                                  float *__restrict__ post, int32_t *__restrict__ iters,
+                                                  const float *__restrict__ init_cv, float *__restrict__ final_cv) {
+  __shared__ float stage[TW][TW + 1];
+  __shared__ unsigned long long unsat_w[16];
+  __shared__ int s_tile;
+  constexpr int kPsl = check_psl_floats<DC>();  // LDS of high runtime degrees (check_update)
+  __shared__ float psl_buf[kPsl > 0 ? 16 * kPsl : 1];
+  float *psl = kPsl > 0 ? psl_buf + wave_id() * kPsl : nullptr;
+  int *counter = (int *)ws;
+  const TileState st =
+      tile_state_block(ws + kPlainHeader + (size_t)blockIdx.x * tile_bytes(g.nnz, g.n), g.nnz, g.n);
+  const int tiles = (B + TW - 1) / TW;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int tile = s_tile;
+    __syncthreads();  // every thread has read s_tile before thread 0 takes the next one
+    if (tile >= tiles) break;  // same value in every thread
+    plain_decode_tile<DC, DV>(g, llr32, llr64, B, max_iters, early_stop, tile, st, hard, post, iters, init_cv,
+                              final_cv, stage, unsat_w, psl);
+    __syncthreads();  // the tile state and the LDS staging are reused by the next tile
+  }
+}
+
+__global__ void reset_tile_counter(int *counter) {
+  if (threadIdx.x == 0) *counter = 0;
+}
+
 // Low check degrees fit in 64 VGPRs, so the kernel can ask for 8 waves per SIMD (more
 // HBM requests in flight); higher degrees would spill their message arrays to scratch
 // under that limit and take the compiler's own register budget instead.
@@ -129,13 +162,7 @@ __global__ void __launch_bounds__(1024)
 
 using namespace ldpc;
 
-size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch) {
-  const size_t tiles = ((size_t)batch + TW - 1) / TW;
-  return tiles * tile_bytes(g->nnz, g->n);
-}
-
 namespace {
-
 using PlainKernel = void (*)(GraphDev, const float *, const double *, int, int, int, char *, uint8_t *, float *,
                              int32_t *, const float *, float *);
 
@@ -155,19 +182,43 @@ PlainKernel pick_plain(const ldpc_graph_s *g) {
   return k;
 }
 
+// Workgroups of ldpc_decode's launch shape (16 waves) the current device holds resident at
+// once; 0 if the runtime cannot say.
+size_t plain_resident_workgroups(const ldpc_graph_s *g) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick_plain(g), 1024, 0) != hipSuccess)
+    return 0;
+  return (size_t)cus * (size_t)per_cu;
+}
 }  // namespace
+
+size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch) {
+  size_t states = ((size_t)batch + TW - 1) / TW;
+  const size_t resident = plain_resident_workgroups(g);
+  if (resident > 0) states = std::min(states, resident);
+  return kPlainHeader + states * tile_bytes(g->nnz, g->n);
+}
+
+size_t plain_min_workspace_bytes(const ldpc_graph_s *g) { return kPlainHeader + tile_bytes(g->nnz, g->n); }
 
 ldpc_status launch_plain_decode(const ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch,
                                 int32_t max_iters, int32_t early_stop, uint8_t *hard, float *post, int32_t *iters,
                                 void *ws, size_t ws_bytes, int32_t waves, hipStream_t stream, const float *init_cv,
                                 float *final_cv) {
-  (void)ws_bytes;
   GraphDev d = graph_dev(g);
   const size_t tiles = ((size_t)batch + TW - 1) / TW;
+  const size_t tb = tile_bytes(g->nnz, g->n);
+  if (ws_bytes < kPlainHeader + tb) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small");
+  // one workgroup per tile state the workspace holds, at most one per tile
+  const size_t grid = std::min(tiles, (ws_bytes - kPlainHeader) / tb);
   PlainKernel k = pick_plain(g);
   const float *l32 = llr_f64 ? nullptr : (const float *)llr;
   const double *l64 = llr_f64 ? (const double *)llr : nullptr;
-  hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * waves), 0, stream, d, l32, l64, (int)batch, (int)max_iters,
+  hipLaunchKernelGGL(reset_tile_counter, dim3(1), dim3(64), 0, stream, (int *)ws);
+  LDPC_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), 0, stream, d, l32, l64, (int)batch, (int)max_iters,
                      (int)(early_stop != 0), (char *)ws, hard, post, iters, init_cv, final_cv);
   LDPC_HIP_CHECK(hipGetLastError());
   return LDPC_OK;

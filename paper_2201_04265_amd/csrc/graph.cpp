@@ -149,7 +149,8 @@ static ldpc_status decode_common(ldpc_graph_t g, const void *llr, int32_t batch,
   if (batch == 0) return LDPC_OK;
   if (!llr || !hard || !post || !iters || !ws) return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)ws & 255) != 0) return set_error(LDPC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (ws_bytes < plain_workspace_bytes(g, batch)) return set_error(LDPC_ERR_INVALID_ARG, "workspace too small");
+  if (ws_bytes < plain_min_workspace_bytes(g))
+    return set_error(LDPC_ERR_INVALID_ARG, "workspace too small for one 64-word tile state");
   return launch_plain_decode(g, llr, (flags & LDPC_LLR_F64) != 0, batch, max_iters, early_stop, hard, post, iters,
                              ws, ws_bytes, waves, stream, init_cv, final_cv);
 }

@@ -105,7 +105,8 @@ ldpc_status stream_ready_for(ldpc_graph_s *g, int32_t threads);
 ldpc_status launch_stream_decode(ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch, int32_t max_iters,
                                  int32_t early_stop, uint8_t *hard_bits, float *posterior, int32_t *iters_used,
                                  int *counter, int32_t threads, hipStream_t stream);
-size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch);
+size_t plain_workspace_bytes(const ldpc_graph_s *g, int32_t batch);  // full speed (decode.hip)
+size_t plain_min_workspace_bytes(const ldpc_graph_s *g);             // one tile state at a time
 // Split form (split.hip): workspace bytes and one enqueued decode (slices = 0: automatic).
 size_t split_workspace_bytes(const ldpc_graph_s *g, int32_t batch);
 ldpc_status launch_split_decode(const ldpc_graph_s *g, const void *llr, bool llr_f64, int32_t batch,
