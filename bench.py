@@ -56,7 +56,7 @@ COUNTERS = {
                "sha1": "83b487ddc6801e9725c89f901567de1433e6c5d6", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": "5ae99b4c9e0cd5b731e4feb1809a89b4d8fcaec0", "bytes_per_launch": 1804880054051},
+              "sha1": "98fa087bed4bb36610729740cd07d537c35d6068", "bytes_per_launch": 1804703858226},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
                 "sha1": "224de4202dc7fe4b9a582c86dec265ec8e3a05ea", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],

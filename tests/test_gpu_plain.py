@@ -82,6 +82,47 @@ def test_random_irregular_codes_ragged_batches(P, oracle_lib, seed):
     assert_parity(st, allow_tie_fraction=0.02)
 
 
+def _tile_bytes(code):
+    """One 64-word tile state: M, E0, E1 [edges][64] and R [n][64] FP32, each 256-byte aligned."""
+    al = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    return 3 * al(code.nnz * 64 * 4) + al(code.n * 64 * 4)
+
+
+@pytest.mark.parametrize("states", [1, 2, 3])
+def test_small_workspace_reuses_tile_states(P, states):
+    """Workgroups take tiles from a counter and reuse their own tile state: a workspace of 256
+    bytes plus 1-3 tile states decodes a ragged 10-tile batch (with early stop, so tiles take
+    different times) to the same bits as the full-speed workspace, through the C ABI; one byte
+    less than a tile state is refused."""
+    import ctypes
+
+    code = workloads.code("c1")
+    g = P.Graph.from_code(code)
+    B = 9 * 64 + 17
+    wd = workloads.words("c1", 1, 0, 1.5, 0, B, fp32=True)
+    x = torch.from_numpy(wd.llr).cuda()
+    ref = P.decode(g, x, 20, True)
+    L = P.lib()
+    need = ctypes.c_size_t()
+    assert L.ldpc_decode_workspace_size(g.handle, B, 0, ctypes.byref(need)) == 0
+    assert need.value <= 256 + 10 * _tile_bytes(code)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    for nbytes, ok in ((256 + states * _tile_bytes(code), True), (255 + _tile_bytes(code), False)):
+        ws = torch.empty((nbytes,), dtype=torch.uint8, device="cuda")
+        h = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+        po = torch.empty((B, code.n), dtype=torch.float32, device="cuda")
+        it = torch.empty((B,), dtype=torch.int32, device="cuda")
+        st = L.ldpc_decode(g.handle, p(x), B, 20, 1, 0, p(h), p(po), p(it), p(ws), nbytes, s)
+        if not ok:
+            assert st == -1
+            continue
+        assert st == 0, L.ldpc_last_error()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, (h, po, it)):
+            assert torch.equal(a, b)
+
+
 def test_noiseless_and_zero_iterations(P):
     code = workloads.code("c2")
     wd = workloads.words("c2", 2, 0, 2.0, 0, 130, fp32=True)
