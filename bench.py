@@ -178,6 +178,14 @@ def make_inputs(args, torch):
     return code, ebn0s, llr, cw
 
 
+def environment(torch):
+    """Software and device the line was measured with."""
+    props = torch.cuda.get_device_properties(0)
+    return {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+            "device": torch.cuda.get_device_name(0), "arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count, "hbm_gib": round(props.total_memory / 2**30, 1)}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -747,16 +755,16 @@ def main():
         return
 
     if args.workload == "c3":
-        print(json.dumps(bench_c3(args, torch, P)), flush=True)
+        print(json.dumps(dict(bench_c3(args, torch, P), env=environment(torch))), flush=True)
         return
     if args.workload == "c4":
-        print(json.dumps(bench_c4(args, torch, P)), flush=True)
+        print(json.dumps(dict(bench_c4(args, torch, P), env=environment(torch))), flush=True)
         return
     if args.workload == "c5":
-        print(json.dumps(bench_c5(args, torch, P)), flush=True)
+        print(json.dumps(dict(bench_c5(args, torch, P), env=environment(torch))), flush=True)
         return
     if args.workload == "paper":
-        print(json.dumps(bench_paper(args, torch, P)), flush=True)
+        print(json.dumps(dict(bench_paper(args, torch, P), env=environment(torch))), flush=True)
         return
 
     code, ebn0s, llr, cw = make_inputs(args, torch)
@@ -874,6 +882,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(code, ebn0s, args.cpu_sample)
+    result["env"] = environment(torch)
     print(json.dumps(result), flush=True)
 
 
