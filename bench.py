@@ -53,12 +53,12 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "83b487ddc6801e9725c89f901567de1433e6c5d6", "bytes_per_launch": 66162809745,
+               "sha1": "8328ad5e2950449b5f792ee6f69dedda02defdea", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
-              "sha1": "98fa087bed4bb36610729740cd07d537c35d6068", "bytes_per_launch": 1804703858226},
+              "sha1": "c02a93dd8358be4266af407fb9e8fd454d47ee16", "bytes_per_launch": 1804703858226},
     "batched": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "multi.hip", "multi.h", "internal.h")],
-                "sha1": "224de4202dc7fe4b9a582c86dec265ec8e3a05ea", "bytes_per_launch": 1552948885069,
+                "sha1": "d3c05932b9d8aa06cf3ae4fb57fd807dba799dfc", "bytes_per_launch": 1552948885069,
                 "shape": {"waves": 16, "slots": [256], "refill": 1, "lanes": 64, "stream_threads": [0],
                           "split_slices": [0], "span": [1]}},
 }

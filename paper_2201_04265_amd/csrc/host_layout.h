@@ -27,7 +27,11 @@ ldpc_status graph_build_host(int32_t m, int32_t n, ldpc_format fmt, const int32_
                              int64_t nnz, GraphHost &g, std::string &err);
 
 // Degree specialisations compiled for the kernels: fixed (dc, dv) pairs, then
-// generic kernels for irregular codes up to a maximum check degree.
+// generic kernels for irregular codes up to a maximum check degree.  The degree-24
+// class also bounds the variable degree (12: quasi-cyclic protographs stay below it), so
+// that its register arrays leave room for the stream form's prefetch of the next
+// variables; codes with a variable of degree 13 to 16 take the degree-32 class.
+constexpr int kG24MaxVarDegree = 12;
 enum KernelKind : int32_t {
   KIND_6_3 = 0,
   KIND_4_3,
@@ -55,7 +59,7 @@ inline int32_t kernel_kind(const GraphHost *g) {
   }
   if (g->dc_max <= 8) return KIND_G8;
   if (g->dc_max <= 16) return KIND_G16;
-  if (g->dc_max <= 24) return KIND_G24;
+  if (g->dc_max <= 24 && g->dv_max <= kG24MaxVarDegree) return KIND_G24;
   return KIND_G32;
 }
 

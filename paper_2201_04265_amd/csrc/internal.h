@@ -77,7 +77,7 @@ inline GraphDev graph_dev(const ldpc_graph_s *g) {
     case KIND_12_9: F(12, 9); break;                      \
     case KIND_G8: F(-8, -LDPC_MAX_VAR_DEGREE); break;     \
     case KIND_G16: F(-16, -LDPC_MAX_VAR_DEGREE); break;   \
-    case KIND_G24: F(-24, -LDPC_MAX_VAR_DEGREE); break;   \
+    case KIND_G24: F(-24, -kG24MaxVarDegree); break;      \
     default: F(-LDPC_MAX_CHECK_DEGREE, -LDPC_MAX_VAR_DEGREE); break; \
   }
 

@@ -90,6 +90,31 @@ def test_irregular_codes(P, oracle_lib, seed, dtype):
     same(a, b)
 
 
+def test_check_degree_24_with_variable_degrees_above_12(P, oracle_lib):
+    """Check degrees up to 24 take the degree-24 class only while every variable degree is at
+    most 12; a code with variables of degree 13 to 16 runs the degree-32 class instead, in
+    every form: stream and plain bit-identical, both at parity with the oracle."""
+    rng = np.random.default_rng(4242)
+    n, m = 220, 100
+    chk, var = [], []
+    for c in range(m):
+        vs = set(rng.choice(np.arange(1, n), size=int(rng.integers(10, 22)), replace=False).tolist())
+        if c < 14:
+            vs.add(0)  # variable 0 in 14 checks
+        chk += [c] * len(vs)
+        var += sorted(vs)
+    code = codes.from_edges(m, n, np.array(chk), np.array(var))
+    assert code.row_degrees().max() <= 24 and 13 <= np.bincount(code.indices, minlength=n).max() <= 16
+    g = P.Graph.from_code(code)
+    llr = rng.normal(2.5, 2.0, size=(150, n)).astype(np.float32)
+    a, b = both(P, g, llr, 20)
+    same(a, b)
+    oh, op, oi, _ = oracle_lib.decode(code, llr, 20, True)
+    st = compare(oh, op, oi, a[0], a[1], a[2], oracle_lib, code, llr, 20)
+    print(st)
+    assert_parity(st, allow_tie_fraction=0.02)
+
+
 def test_mixed_batch_codes(P):
     """Every mixed-batch code that fits the LDS of a workgroup decodes identically in both forms."""
     for i, name in enumerate(W.C4_CODES):
