@@ -301,7 +301,7 @@ ldpc_status ldpc_plan_destroy(ldpc_plan_t plan);
  * code's span doubled and halved.  Candidates that the launch cannot take (group slots beyond
  * the resident capacity) are skipped.  Every candidate runs once to warm up and then 2 to 16 times
  * (about 40 ms in all); its time is the median.  The winner and the automatic start are timed
- * again at the end, and the faster of the two is returned.
+ * again at the end, and the start is returned unless the winner is more than 2 % faster.
  * Writes the jobs' outputs; allocates and frees its own temporary workspace (the largest
  * any candidate needs).  Synchronises `stream`.
  */

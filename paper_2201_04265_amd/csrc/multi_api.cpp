@@ -310,12 +310,13 @@ extern "C" ldpc_status ldpc_autotune_multi(const ldpc_graph_t *graphs, int32_t n
     }
   }
   // 5. the winner against the automatic start, timed again side by side: a search decided by
-  // one noisy measurement must not return a shape slower than the heuristics
+  // one noisy measurement must not return a shape slower than the heuristics, so the start
+  // stays unless the winner is faster by more than the timing noise (2 %)
   if (st == LDPC_OK) {
     float again = 0, start_again = 0;
     st = T.time(cur, &again);
     if (st == LDPC_OK) st = T.time(start_shape, &start_again);
-    if (st == LDPC_OK && start_again < again) {
+    if (st == LDPC_OK && start_again <= again * 1.02f) {
       cur = start_shape;
       cur_ms = start_again;
     } else if (st == LDPC_OK) {

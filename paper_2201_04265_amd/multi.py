@@ -180,7 +180,7 @@ def _signature(graphs, batch: Batch, early_stop) -> str:
         h.update(c.tobytes())
         h.update(v.tobytes())
         h.update(f"{g.m},{g.n},{x.shape[0]},{j.max_iters};".encode())
-    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName};shape-v3".encode())
+    h.update(f"es={int(bool(early_stop))};{torch.cuda.get_device_properties(0).gcnArchName};shape-v4".encode())
     return h.hexdigest()
 
 
