@@ -53,7 +53,7 @@ METRIC = "coded Gbit/s + edge updates/s, (3,6) n=4096 sum-product; plain vs batc
 _CSRC = "paper_2201_04265_amd/csrc/"
 COUNTERS = {
     "stream": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "stream.hip", "internal.h")],
-               "sha1": "8328ad5e2950449b5f792ee6f69dedda02defdea", "bytes_per_launch": 66162809745,
+               "sha1": "8b15aee5b3939f7402f5e6fc91ee4c0334768803", "bytes_per_launch": 66162809745,
                "valu_insts_per_launch": 43903137112},
     "plain": {"sources": [_CSRC + f for f in ("spa_core.h", "tile.h", "decode.hip", "internal.h")],
               "sha1": "c02a93dd8358be4266af407fb9e8fd454d47ee16", "bytes_per_launch": 1804703858226},

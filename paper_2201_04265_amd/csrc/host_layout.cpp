@@ -169,11 +169,15 @@ std::vector<int32_t> stream_group_table(const GraphHost *g, const StreamGroupLay
     tab[L.slot.size() + 3 * i] = k;
     tab[L.slot.size() + 3 * i + 1] = (int32_t)start;
     tab[L.slot.size() + 3 * i + 2] = gmin == gd ? gd : -1;
-    tab.resize(start + 64 * (size_t)(gd + 1), 0);
+    tab.resize(start + 64 * (size_t)(1 + (gd + 1) / 2), 0);
     for (int v = v0; v < v1; ++v) {
       tab[start + (v & 63)] = g->var_ptr[v + 1] - g->var_ptr[v];
-      for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p)
-        tab[start + 64 * (size_t)(p - g->var_ptr[v] + 1) + (v & 63)] = var_off[(size_t)p];
+      for (int32_t p = g->var_ptr[v]; p < g->var_ptr[v + 1]; ++p) {
+        const int j = p - g->var_ptr[v];
+        const uint32_t idx = (uint32_t)var_off[(size_t)p] / 4u;  // LDS float index, < 2^16
+        uint32_t &w = reinterpret_cast<uint32_t &>(tab[start + 64 * (size_t)(1 + j / 2) + (v & 63)]);
+        w |= (idx & 0xffffu) << (16 * (j & 1));
+      }
     }
   }
   return tab;

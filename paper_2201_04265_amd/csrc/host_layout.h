@@ -76,9 +76,10 @@ StreamGroupLayout stream_group_layout(const GraphHost *g);
 // Stream form, runtime degrees: the kernel's table.  The check slots of L; then, per position
 // of L.var_order, the group, where its rows start and its degree when all its variables share
 // one (else -1); then the rows, group by group: the 64 lanes' degrees, then their edges' LDS
-// byte offsets (var_off, in var_edges order), entry j of lane l at start + 64 (j + 1) + l, so
-// that a wavefront reads each row as one contiguous 256-byte segment (64 x (1 + the group's
-// largest degree) entries).
+// float indices (var_off / 4, var_off in var_edges order), two to an entry: index j of lane l
+// in bits 16 (j mod 2) .. +15 of entry start + 64 (1 + j / 2) + l, so that a wavefront reads
+// each row as one contiguous 256-byte segment (64 x (1 + half the group's largest degree,
+// rounded up) entries).  LDS indices fit 16 bits: a workgroup's LDS holds fewer floats.
 std::vector<int32_t> stream_group_table(const GraphHost *g, const StreamGroupLayout &L,
                                         const std::vector<int32_t> &var_off);
 // Stream form, fixed check degrees: each variable edge's LDS byte offset (var_edges order)

@@ -143,22 +143,32 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
       const float *__restrict__ lrow32 = llr32 + base;
       const double *__restrict__ lrow64 = llr64 + base;
       float *__restrict__ prow = post + base;
+      // A variable's edge offsets: byte offsets for fixed degrees; for runtime degrees the
+      // LDS float indices (< 2^16) two to a register, which leaves room for a third set.
+      constexpr int kOffRegs = DV > 0 ? DVM : (DVM + 1) / 2;
       struct VarIn {
-        int off[DVM];
+        int off[kOffRegs];
         int dv;
         float r;
       };
+      auto offj = [](const VarIn &f, int j) -> int {
+        if constexpr (DV > 0)
+          return f.off[j];
+        else
+          return (int)((((uint32_t)f.off[j >> 1]) >> ((j & 1) << 4)) & 0xffffu) << 2;
+      };
       // (32-bit byte offsets from uniform bases: the loads take an SGPR base address)
-      auto fetch = [&](int vv, VarIn &f) {
-        int p0;
-        var_range<DV>(g, vv, p0, f.dv);
-        f.r = F64 ? (float)*(const double *)((const char *)lrow64 + (uint32_t)vv * 8u)
-                  : *(const float *)((const char *)lrow32 + (uint32_t)vv * 4u);
-        const uint32_t pb = DV > 0 ? __umul24((uint32_t)vv, 4u * DVM) : (uint32_t)p0 * 4u;
-        const int32_t *__restrict__ ve = (const int32_t *)((const char *)g.var_xoff + pb);
+      auto fetch = [&](int vv, VarIn &f) {  // fixed degrees
+        if constexpr (DV > 0) {
+          int p0;
+          var_range<DV>(g, vv, p0, f.dv);
+          f.r = F64 ? (float)*(const double *)((const char *)lrow64 + (uint32_t)vv * 8u)
+                    : *(const float *)((const char *)lrow32 + (uint32_t)vv * 4u);
+          const int32_t *__restrict__ ve =
+              (const int32_t *)((const char *)g.var_xoff + __umul24((uint32_t)vv, 4u * DVM));
 #pragma unroll
-        for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < f.dv) f.off[j] = ve[j];
+          for (int j = 0; j < DVM; ++j) f.off[j] = ve[j];
+        }
       };
       // X is the kernel's only LDS, so it starts at LDS address 0 (checked on the host)
       // and an edge's byte offset is its LDS address.
@@ -167,14 +177,14 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
         float ev[DVM];
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < dv) ev[j] = *xat(f.off[j]);
+          if (DV > 0 || j < dv) ev[j] = *xat(offj(f, j));
         const double L = var_total<DV>(f.r, ev, dv);
         const float Lf = (float)L;
         *(float *)((char *)prow + (uint32_t)v * 4u) = Lf;
         const bool z = Lf <= 0.0f;
 #pragma unroll
         for (int j = 0; j < DVM; ++j)
-          if (DV > 0 || j < dv) *xat(f.off[j]) = v2c_store(var_extrinsic(L, ev[j]), z);
+          if (DV > 0 || j < dv) *xat(offj(f, j)) = v2c_store(var_extrinsic(L, ev[j]), z);
       };
       auto update = [&](int v, const VarIn &f) {
         if constexpr (DV > 0) {
@@ -241,20 +251,26 @@ __global__ void __launch_bounds__(kStreamMaxThreads<DC>)
           f.r = F64 ? (float)*(const double *)((const char *)lrow64 + (uint32_t)v * 8u)
                     : *(const float *)((const char *)lrow32 + (uint32_t)v * 4u);
 #pragma unroll
-          for (int j = 0; j < DVM; ++j)
-            if (j < f.dv) f.off[j] = ve[(j + 1) << 6];
+          for (int r = 0; r < kOffRegs; ++r)
+            if (2 * r < f.dv) f.off[r] = ve[(r + 1) << 6];
         };
-        VarIn fa, fb;
-        int ka = next_group(s_next + 1), va = 0, vb = 0;
+        VarIn fa, fb, fc;
+        int ka = next_group(s_next + 1), va = 0, vb = 0, vc = 0;
         if (ka < vgroups) fetch_group(ka, va, fa);
+        int kb = next_group(s_next + 1);
+        if (kb < vgroups) fetch_group(kb, vb, fb);
         while (ka < vgroups) {
-          const int kb = next_group(s_next + 1);
-          if (kb < vgroups) fetch_group(kb, vb, fb);
+          const int kc = next_group(s_next + 1);
+          if (kc < vgroups) fetch_group(kc, vc, fc);
           if (va < g.n) update(va, fa);
           if (kb >= vgroups) break;
           ka = next_group(s_next + 1);
           if (ka < vgroups) fetch_group(ka, va, fa);
           if (vb < g.n) update(vb, fb);
+          if (kc >= vgroups) break;
+          kb = next_group(s_next + 1);
+          if (kb < vgroups) fetch_group(kb, vb, fb);
+          if (vc < g.n) update(vc, fc);
         }
       } else {
         // two sets (the higher fixed degrees would lose resident waves to a third)

@@ -131,11 +131,15 @@ static void check_layouts(const GraphHost &g) {
         gd = std::max(gd, d);
         gmin = std::min(gmin, d);
         CHECK(tab[(size_t)start + (v & 63)] == d);
-        for (int j = 0; j < d; ++j)
-          CHECK(tab[(size_t)start + 64 * (j + 1) + (v & 63)] == off[(size_t)g.var_ptr[v] + j]);
+        for (int j = 0; j < d; ++j) {
+          const uint32_t w = (uint32_t)tab[(size_t)start + 64 * (1 + j / 2) + (v & 63)];
+          CHECK(((w >> (16 * (j & 1))) & 0xffffu) * 4u == (uint32_t)off[(size_t)g.var_ptr[v] + j]);
+        }
+        if (d % 2 == 1)  // the unused half of the last entry stays 0
+          CHECK(((uint32_t)tab[(size_t)start + 64 * (1 + d / 2) + (v & 63)] >> 16) == 0u);
       }
       CHECK(ud == (gmin == gd ? gd : -1));
-      end = (size_t)start + 64 * (size_t)(gd + 1);
+      end = (size_t)start + 64 * (size_t)(1 + (gd + 1) / 2);
     }
     CHECK(tab.size() == end);
   } else {
