@@ -1,13 +1,14 @@
 """ldpc_decode_noalloc (no device allocation, fixed scratch array) against ldpc_decode, through
-the C ABI: bit-identical outputs on two calls in a row, the second with a smaller batch, and
-a clear error for a batch whose tile state exceeds the fixed array."""
+the C ABI: bit-identical outputs on two calls in a row, the second with a smaller batch; a
+clear error for a batch whose tile state exceeds the fixed array; and any batch of a code
+small enough that the resident workgroups' tile states fit the array (tiles taken in turn)."""
 import ctypes
 
 import numpy as np
 import pytest
 import torch
 
-from synth import workloads
+from synth import codes, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -80,3 +81,23 @@ def test_noalloc_rejects_batch_above_the_array():
     st = L.ldpc_decode_noalloc(g.handle, _p(x), B, 50, 1, 0, _p(h), _p(p), _p(i), s)
     assert st == -1
     assert b"scratch" in L.ldpc_last_error()
+
+
+def test_noalloc_small_code_any_batch():
+    """A (3,6) n=48 code: 512 resident tile states of 123 kB fit the 64 MiB array, so a batch of
+    700 tiles (more than the array or the GPU holds at once) is accepted; workgroups take the
+    tiles in turn and the outputs equal ldpc_decode's."""
+    import paper_2201_04265_amd as P
+
+    L = P.lib()
+    code = codes.gallager_band(48, 3, 6, codes.rng_for(77, 0), "band(3,6)n48")
+    g = P.Graph.from_code(code)
+    B = 700 * 64 - 5
+    rng = np.random.default_rng(78)
+    x = torch.from_numpy(rng.normal(1.2, 1.6, size=(B, code.n)).astype(np.float32)).cuda()
+    print("n=48 batch", B, flush=True)
+    ref = _reference(L, g, x, 30, True, False)
+    got = _noalloc(L, g, x, 30, True, False)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
