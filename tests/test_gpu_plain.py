@@ -123,6 +123,30 @@ def test_small_workspace_reuses_tile_states(P, states):
             assert torch.equal(a, b)
 
 
+def test_full_speed_workspace_is_bounded_by_resident_workgroups(P):
+    """ldpc_decode_workspace_size: 256 bytes plus one tile state per workgroup the device keeps
+    resident (at most one per tile), so the 327 680-word C2 batch asks for its 512 resident
+    workgroups' states (5.4 GB), not for its 5120 tiles' (54 GB); a batch of fewer tiles asks
+    for exactly its tiles."""
+    import ctypes
+
+    code = workloads.code("c2")
+    g = P.Graph.from_code(code)
+    L = P.lib()
+    tb = _tile_bytes(code)
+    props = torch.cuda.get_device_properties(0)
+    for B, states in ((5 * 65536, None), (3 * 64 + 1, 4)):
+        need = ctypes.c_size_t()
+        assert L.ldpc_decode_workspace_size(g.handle, B, 0, ctypes.byref(need)) == 0
+        assert (need.value - 256) % tb == 0
+        got = (need.value - 256) // tb
+        if states is None:
+            assert 1 <= got <= 4 * props.multi_processor_count < (B + 63) // 64
+            print("C2 batch", B, "tile states", got, "bytes", need.value, flush=True)
+        else:
+            assert got == states
+
+
 def test_noiseless_and_zero_iterations(P):
     code = workloads.code("c2")
     wd = workloads.words("c2", 2, 0, 2.0, 0, 130, fp32=True)
