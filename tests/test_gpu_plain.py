@@ -166,6 +166,32 @@ def test_empty_batch_is_noop(P):
     assert hard.shape == (0, code.n) and iters.shape == (0,)
 
 
+def test_empty_batch_every_form(P):
+    """An empty batch returns at once in every single-code entry point (no buffer is touched, so
+    the binding's zero-size tensors with NULL data may be passed); the adjoint of the unrolled
+    decoder still writes its weight gradient, which is zero."""
+    import ctypes
+
+    code = workloads.code("c1")
+    g = P.Graph.from_code(code)
+    for dtype in (torch.float32, torch.float64):
+        t = torch.zeros((0, code.n), dtype=dtype, device="cuda")
+        for fn in (P.decode_ex, P.decode_stream, P.decode_split):
+            hard, post, iters = fn(g, t, 20)[:3]
+            assert hard.shape == (0, code.n) and post.shape == (0, code.n) and iters.shape == (0,)
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        flags = 1 if dtype == torch.float64 else 0
+        assert P.lib().ldpc_decode_noalloc(g.handle, None, 0, 20, 1, flags, None, None, None, s) == 0
+    t = torch.zeros((0, code.n), dtype=torch.float32, device="cuda", requires_grad=True)
+    w = torch.full((4, g.edges), 0.5, dtype=torch.float32, device="cuda", requires_grad=True)
+    post = P.unrolled_decode(g, t, w)
+    assert post.shape == (0, code.n)
+    post.sum().backward()
+    torch.cuda.synchronize()
+    assert t.grad.shape == (0, code.n)
+    assert torch.count_nonzero(w.grad).item() == 0
+
+
 def test_fixed_iterations_without_early_stop(P, oracle_lib):
     code = workloads.code("c1")
     wd = workloads.words("c1", 1, 0, 2.0, 0, 200, fp32=True)
