@@ -416,6 +416,16 @@ ldpc_status ldpc_generate(ldpc_encoder_t e, int32_t batch, uint64_t seed, uint64
 ldpc_status ldpc_count_errors(ldpc_encoder_t e, const uint8_t *hard, const uint8_t *cw, int32_t batch,
                               uint64_t *counts, hipStream_t stream);
 
+/*
+ * Syndrome test of Eq. 1 (H z^T = 0 over GF(2)) on a batch of hard decisions, the
+ * test the decoders apply to stop a word early: ok[b] = 1 iff every check of g has an
+ * even number of ones among word b's decisions, else 0.  hard_bits: device
+ * [batch][n] bytes (nonzero = 1), e.g. a decoder's hard_bits; ok: device [batch]
+ * bytes, written.  Tells a word that satisfies every check at the iteration limit
+ * (iters_used = max_iters) from one that does not.  batch = 0 is a no-op.
+ */
+ldpc_status ldpc_syndrome(ldpc_graph_t g, const uint8_t *hard_bits, int32_t batch, uint8_t *ok, hipStream_t stream);
+
 const char *ldpc_status_string(ldpc_status s);
 const char *ldpc_last_error(void);
 

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 from ._lib import LdpcError, lib, library_path  # noqa: F401
 from .graph import Graph  # noqa: F401
-from .decoder import decode, decode_ex, decode_split, decode_stream, split_workspace_size, stream_lds_bytes, stream_supported, workspace_size  # noqa: F401,E501
+from .decoder import decode, decode_ex, decode_split, decode_stream, split_workspace_size, stream_lds_bytes, stream_supported, syndrome_ok, workspace_size  # noqa: F401,E501
 from .multi import SPLIT_AUTO, STREAM_AUTO, Batch, Plan, Shape, decode_multi, fault, tuned_shape  # noqa: F401
 from .unrolled import UnrolledBP, unrolled_decode  # noqa: F401
 from .encoder import Encoder, channel_awgn  # noqa: F401

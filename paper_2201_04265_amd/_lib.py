@@ -50,6 +50,7 @@ SIGNATURES = {
     "ldpc_generate": ([_p, _i32, ctypes.c_uint64, ctypes.c_uint64, _i64, ctypes.c_double, _u32, _p, _p, _p, _p],
                       ctypes.c_int),
     "ldpc_count_errors": ([_p, _p, _p, _i32, _p, _p], ctypes.c_int),
+    "ldpc_syndrome": ([_p, _p, _i32, _p, _p], ctypes.c_int),
     "ldpc_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "ldpc_last_error": ([], ctypes.c_char_p),
 }

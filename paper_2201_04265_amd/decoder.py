@@ -155,3 +155,14 @@ def decode_split(graph: Graph, llr: torch.Tensor, max_iters: int, early_stop: bo
                                   _ptr(hard), _ptr(post), _ptr(iters), _ptr(workspace), workspace.numel(),
                                   int(slices), ctypes.c_void_p(stream_handle(stream))))
     return hard, post, iters
+
+
+def syndrome_ok(graph: Graph, hard: torch.Tensor, stream=None) -> torch.Tensor:
+    """ldpc_syndrome: uint8 [B], 1 where H z^T = 0 for the decisions hard [B, n] (uint8, nonzero = 1)."""
+    if not hard.is_cuda or hard.dtype != torch.uint8 or hard.dim() != 2 or hard.shape[1] != graph.n:
+        raise ValueError("hard must be a cuda uint8 tensor of shape [B, n]")
+    hard = hard.contiguous()
+    ok = torch.empty((hard.shape[0],), dtype=torch.uint8, device=hard.device)
+    check("ldpc_syndrome", lib().ldpc_syndrome(graph.handle, _ptr(hard), hard.shape[0], _ptr(ok),
+                                               ctypes.c_void_p(stream_handle(stream))))
+    return ok

@@ -172,3 +172,29 @@ def test_reference_gradient_single_check_closed_form():
                 rest = np.prod(th[[x for x in others if x != u]])
                 expect = 2.0 / (1 - p * p) * rest * 0.5 * (1 - th[u] ** 2)
             assert J[v, u] == pytest.approx(expect, rel=1e-10, abs=1e-12)
+
+
+@pytest.mark.parametrize("which", ["fig1", "irregular"])
+def test_syndrome_ok_is_the_codebook(oracle_lib, which):
+    """Over every n-bit word of a small code, the words that pass the oracle's syndrome test
+    (Eq. 1) are exactly the 2^k codewords m G of the systematic generator (Eqs. 2-3), which the
+    oracle builds by row reduction, not by the syndrome."""
+    from oracle import encode as OE
+    from oracle import map as OM
+
+    if which == "fig1":
+        code = codes.fig1_matrix()
+    else:
+        rng = np.random.default_rng(3)
+        H = np.zeros((6, 12), dtype=np.uint8)
+        for c in range(6):
+            H[c, rng.choice(12, size=int(rng.integers(2, 6)), replace=False)] = 1
+        code = codes.from_dense(H, "irregular")
+    n = code.n
+    allw = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.uint8)
+    ok = oracle_lib.syndrome_ok(code, allw)
+    form = OE.systematic(code)
+    book = OM.codebook(form.G)
+    assert int(ok.sum()) == len(book) == 1 << form.k
+    assert {tuple(r) for r in allw[ok == 1]} == {tuple(r) for r in book}
+
