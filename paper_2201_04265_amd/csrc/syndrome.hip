@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kSynThreads)
                            const uint8_t *__restrict__ hard, int batch, uint8_t *__restrict__ ok) {
   extern __shared__ __align__(16) uint32_t zb[];
   __shared__ uint32_t s_unsat[2];  // by group parity: cleared two groups after its last read
-  const int groups = (batch + kSynWords - 1) / kSynWords;
+  const int groups = batch / kSynWords + (batch % kSynWords != 0);  // no overflow near INT32_MAX
   int parity = 0;
   for (int grp = blockIdx.x; grp < groups; grp += gridDim.x, parity ^= 1) {
     const int b0 = grp * kSynWords;
@@ -126,7 +126,7 @@ extern "C" ldpc_status ldpc_syndrome(ldpc_graph_t g, const uint8_t *hard_bits, i
   if (batch == 0) return LDPC_OK;
   if (!hard_bits || !ok) return set_error(LDPC_ERR_INVALID_ARG, "NULL buffer");
   if (g->n <= kSynPackedMaxN) {
-    const int32_t groups = (batch + kSynWords - 1) / kSynWords;
+    const int32_t groups = batch / kSynWords + (batch % kSynWords != 0);
     const unsigned grid = (unsigned)std::min<int32_t>(groups, kSynMaxGrid);
     const size_t lds = (size_t)g->n * 4;
     const bool vec = (g->n & 3) == 0 && ((uintptr_t)hard_bits & 3) == 0;
