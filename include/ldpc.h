@@ -9,6 +9,8 @@
  * may end each word early.
  *
  * Conventions shared by every entry point
+ *  - batch (words per call) is at most 2^31 - 64: tile counts are (batch + 63) / 64 in
+ *    32-bit arithmetic.  Split larger batches into several calls.
  *  - H is m x n.  Edges are numbered in CSR order: check-major, variables
  *    ascending inside a check.  Per-edge arrays (weights, gradients) use it.
  *  - LLRs are log P(c=0)/P(c=1) (BPSK x = 1 - 2c gives lambda = 2y/sigma^2,
